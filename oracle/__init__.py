@@ -1,0 +1,11 @@
+"""CPU oracle for the multigrid curvature-energy minimisation (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP path.
+
+``liboracle.so`` is compiled from ``mgc_oracle.c`` with gcc (FP64, optional
+OpenMP across the blocks of one colour); see :func:`build`.
+"""
+from .oracle import (  # noqa: F401
+    build, lib_path, OracleParams, SolveInfo, Oracle, default_levels,
+)

@@ -1,0 +1,197 @@
+"""ctypes front end of the FP64 C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mgc_oracle.c")
+
+
+def lib_path() -> str:
+    # MGC_ORACLE_LIB lets the mutation test load a deliberately broken build.
+    return os.environ.get("MGC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2, FP64, OpenMP; no fast-math)."""
+    out = lib_path()
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+class OracleParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
+                ("kind", C.c_int32), ("levels", C.c_int32), ("fine_colours", C.c_int32),
+                ("samples", C.c_int32), ("bisections", C.c_int32), ("round_f32", C.c_int32),
+                ("threads", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("s", C.c_double), ("fs", C.c_double), ("K0", C.c_double), ("Kf", C.c_double),
+                ("rho", C.c_double), ("c_sample", C.c_double), ("c_bisect", C.c_double),
+                ("c_tilde", C.c_double), ("delta", C.c_double), ("c", C.c_double),
+                ("istar", C.c_int32), ("accepted", C.c_int32)]
+
+
+def default_levels(h: int, w: int) -> int:
+    """J = ceil(log2(max(H, W))): the coarsest level still has two blocks along the longer side."""
+    return max(1, int(math.ceil(math.log2(max(h, w)))))
+
+
+_DP = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.environ.get("MGC_ORACLE_LIB") and (
+                not os.path.exists(lib_path()) or os.path.getmtime(lib_path()) < os.path.getmtime(_SRC)):
+            build(force=True)
+        L = C.CDLL(lib_path())
+        P = C.POINTER(OracleParams)
+        L.orc_curvature_at.restype = C.c_double
+        L.orc_curvature_at.argtypes = [C.c_int, _DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_curvature_map.restype = None
+        L.orc_curvature_map.argtypes = [C.c_int, _DP, C.c_int, C.c_int, C.c_double, _DP]
+        L.orc_energy.restype = C.c_double
+        L.orc_energy.argtypes = [C.c_int, _DP, _DP, C.c_int, C.c_int, C.c_double]
+        for name in ("orc_ring_K", "orc_ring_dK"):
+            fn = getattr(L, name)
+            fn.restype = C.c_double
+            fn.argtypes = [C.c_int, _DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_ring_K_many.restype = None
+        L.orc_ring_K_many.argtypes = [C.c_int, _DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                      _DP, C.c_int, _DP]
+        L.orc_ring_size.restype = C.c_int
+        L.orc_ring_size.argtypes = [_DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_local_delta.restype = C.c_double
+        L.orc_local_delta.argtypes = [P, _DP, _DP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_local_solve.restype = C.c_double
+        L.orc_local_solve.argtypes = [P, _DP, _DP, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(SolveInfo)]
+        L.orc_sweep.restype = C.c_int
+        L.orc_sweep.argtypes = [P, _DP, _DP, C.c_int, C.c_int, C.c_void_p]
+        L.orc_vcycle.restype = None
+        L.orc_vcycle.argtypes = [P, _DP, _DP]
+        L.orc_solve.restype = C.c_int
+        L.orc_solve.argtypes = [P, _DP, _DP, C.c_double, C.c_int, C.c_void_p]
+        L.orc_num_colours.restype = C.c_int
+        L.orc_num_colours.argtypes = [P, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def curvature_map(kind: int, u, h: float = 1.0) -> np.ndarray:
+    u = _f64(u)
+    out = np.empty_like(u)
+    _load().orc_curvature_map(kind, u, u.shape[0], u.shape[1], h, out)
+    return out
+
+
+def energy(kind: int, u, f, alpha: float) -> float:
+    u = _f64(u)
+    f = _f64(f)
+    return _load().orc_energy(kind, u, f, u.shape[0], u.shape[1], alpha)
+
+
+class Oracle:
+    """FP64 reference solver for one image (Algorithm 3 with the local solver of reading R8)."""
+
+    def __init__(self, height: int, width: int, alpha: float, kind: int = 0, levels: int = 0,
+                 fine_colours: int = 4, samples: int = 16, bisections: int = 32,
+                 round_f32: bool = False, threads: int = 1):
+        if levels <= 0:
+            levels = default_levels(height, width)
+        self.p = OracleParams(height, width, float(alpha), kind, levels, fine_colours,
+                              samples, bisections, int(bool(round_f32)), threads)
+        self.L = _load()
+
+    # geometry -------------------------------------------------------------
+    @property
+    def levels(self) -> int:
+        return self.p.levels
+
+    def block_side(self, level: int) -> int:
+        return 1 << (level - 1)
+
+    def grid(self, level: int) -> tuple[int, int]:
+        b = self.block_side(level)
+        return (-(-self.p.height // b), -(-self.p.width // b))
+
+    def block_bounds(self, level: int, p: int, q: int) -> tuple[int, int, int, int]:
+        b = self.block_side(level)
+        return (p * b, min((p + 1) * b, self.p.height), q * b, min((q + 1) * b, self.p.width))
+
+    def num_colours(self, level: int) -> int:
+        return self.L.orc_num_colours(C.byref(self.p), level)
+
+    def colour_of(self, level: int, p: int, q: int) -> int:
+        if self.num_colours(level) == 9:
+            return 3 * (p % 3) + (q % 3)
+        return 2 * (p % 2) + (q % 2)
+
+    # local quantities -----------------------------------------------------
+    def ring_K(self, u, bounds, c: float) -> float:
+        u = _f64(u)
+        return self.L.orc_ring_K(self.p.kind, u, self.p.height, self.p.width, *bounds, c)
+
+    def ring_K_many(self, u, bounds, cs) -> np.ndarray:
+        u = _f64(u)
+        cs = _f64(cs)
+        out = np.empty_like(cs)
+        self.L.orc_ring_K_many(self.p.kind, u, self.p.height, self.p.width, *bounds, cs, cs.size, out)
+        return out
+
+    def ring_dK(self, u, bounds, c: float) -> float:
+        u = _f64(u)
+        return self.L.orc_ring_dK(self.p.kind, u, self.p.height, self.p.width, *bounds, c)
+
+    def ring_size(self, u, bounds) -> int:
+        u = _f64(u)
+        return self.L.orc_ring_size(u, self.p.height, self.p.width, *bounds)
+
+    def local_delta(self, u, f, bounds, c: float) -> float:
+        return self.L.orc_local_delta(C.byref(self.p), _f64(u), _f64(f), *bounds, c)
+
+    def local_solve(self, u, f, bounds) -> SolveInfo:
+        info = SolveInfo()
+        self.L.orc_local_solve(C.byref(self.p), _f64(u), _f64(f), *bounds, C.byref(info))
+        return info
+
+    # sweeps / cycles ------------------------------------------------------
+    def sweep(self, u: np.ndarray, f, level: int, colour: int, want_c: bool = False):
+        """In-place colour sweep on a float64 C-contiguous u; returns the c grid if asked."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        cb = None
+        if want_c:
+            cb = np.full(self.grid(level), np.nan)
+        self.L.orc_sweep(C.byref(self.p), u, _f64(f), level, colour,
+                         cb.ctypes.data if cb is not None else None)
+        return cb
+
+    def vcycle(self, u: np.ndarray, f) -> None:
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        self.L.orc_vcycle(C.byref(self.p), u, _f64(f))
+
+    def solve(self, u: np.ndarray, f, rel_tol: float = 1e-6, max_vcycles: int = 1000):
+        """In-place solve; returns (vcycles_done, energy trace E_0..E_done)."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        trace = np.zeros(max_vcycles + 1)
+        n = self.L.orc_solve(C.byref(self.p), u, _f64(f), rel_tol, max_vcycles, trace.ctypes.data)
+        return n, trace[: n + 1].copy()
+
+    def energy(self, u, f) -> float:
+        return energy(self.p.kind, u, f, self.p.alpha)

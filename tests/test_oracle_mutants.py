@@ -1,0 +1,70 @@
+"""Mutation check of the oracle pins: each plausible mistake planted in a copy of the
+oracle source (a dropped term, a wrong sign or index, a swapped branch) must make
+at least one pin in test_oracle_pins.py fail.  Runs on the CPU only."""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "mgc_oracle.c")
+
+# (name, original text, mutated text); every original must occur in the source.
+MUTANTS = [
+    ("mc_wrong_pairing", "double num = (1.0 + uy * uy) * uxx - 2.0 * ux * uy * uxy + (1.0 + ux * ux) * uyy;\n        return num",
+     "double num = (1.0 + ux * ux) * uxx - 2.0 * ux * uy * uxy + (1.0 + uy * uy) * uyy;\n        return num"),
+    ("mc_drop_cross_term", "double num = (1.0 + uy * uy) * uxx - 2.0 * ux * uy * uxy + (1.0 + ux * ux) * uyy;\n        return num",
+     "double num = (1.0 + uy * uy) * uxx + (1.0 + ux * ux) * uyy;\n        return num"),
+    ("uxy_sign", "double uxy = (t[2][2] - t[0][2] - t[2][0] + t[0][0]) / (4.0 * h * h);\n    double q = 1.0 + ux * ux + uy * uy;\n    if (kind == ORC_MC) {\n        /* div",
+     "double uxy = (t[2][2] + t[0][2] - t[2][0] - t[0][0]) / (4.0 * h * h);\n    double q = 1.0 + ux * ux + uy * uy;\n    if (kind == ORC_MC) {\n        /* div"),
+    ("mc_power", "return num / pow(q, 1.5);", "return num / pow(q, 1.0);"),
+    ("gc_power", "return (uxx * uyy - uxy * uxy) / (q * q);", "return (uxx * uyy - uxy * uxy) / q;"),
+    ("gc_det_sign", "return (uxx * uyy - uxy * uxy) / (q * q);", "return (uxx * uyy + uxy * uxy) / (q * q);"),
+    ("ring_misses_outer", "double acc = 0.0;\n    for (int i = r0 - 1; i <= r1; ++i) {\n        if (i < 0 || i >= H) continue;\n        for (int j = c0 - 1; j <= c1; ++j) {\n            if (j < 0 || j >= W) continue;\n            double t[3][3], m[3][3];\n            int n = shifted_taps(u, H, W, i, j, r0, r1, c0, c1, c, t, m);\n            if (n == 0 || n == 9) continue;\n            acc += fabs",
+     "double acc = 0.0;\n    for (int i = r0; i < r1; ++i) {\n        if (i < 0 || i >= H) continue;\n        for (int j = c0; j < c1; ++j) {\n            if (j < 0 || j >= W) continue;\n            double t[3][3], m[3][3];\n            int n = shifted_taps(u, H, W, i, j, r0, r1, c0, c1, c, t, m);\n            if (n == 0 || n == 9) continue;\n            acc += fabs"),
+    ("border_wrap_not_clamp", "t[dy + 1][dx + 1] = u[(size_t)ci * W + cj] + (inb ? c : 0.0);",
+     "t[dy + 1][dx + 1] = u[(size_t)ci * W + cj] + ((inb || (ci == i && cj == j)) ? c : 0.0);"),
+    ("energy_data_factor", "e += fabs(orc_curvature_at(kind, u, H, W, i, j, 1.0)) + 0.5 * alpha * d * d;",
+     "e += fabs(orc_curvature_at(kind, u, H, W, i, j, 1.0)) + alpha * d * d;"),
+    ("delta_data_sign", "return (Kc - K0) + 0.5 * P->alpha * s * c * (c - 2.0 * fs);",
+     "return (Kc - K0) + 0.5 * P->alpha * s * c * (c + 2.0 * fs);"),
+    ("bisection_direction", "if (d > 0.0) hi = mid; else lo = mid;", "if (d > 0.0) lo = mid; else hi = mid;"),
+    ("derivative_no_sign", "double s = (k > 0.0) - (k < 0.0);", "double s = 1.0;"),
+    ("bracket_too_narrow", "const double rho = sqrt(2.0 * Kf / as);", "const double rho = sqrt(0.05 * Kf / as);"),
+    ("mean_not_sum", "const double fs = r / s;", "const double fs = r;"),
+    ("no_accept_test", "int accepted = delta < eta;", "int accepted = 1;"),
+    ("colour_map", "return ncol == 9 ? 3 * (p % 3) + (q % 3) : 2 * (p % 2) + (q % 2);",
+     "return ncol == 9 ? 3 * (p % 3) + (q % 3) : 2 * (q % 2) + (p % 2);"),
+]
+
+
+def _build_mutant(tmp, name, old, new):
+    src = open(SRC).read()
+    assert old in src, name
+    path_c = os.path.join(tmp, name + ".c")
+    with open(path_c, "w") as fh:
+        fh.write(src.replace(old, new, 1))
+    path_so = os.path.join(tmp, name + ".so")
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                           path_c, "-o", path_so, "-lm"])
+    return path_so
+
+
+def _run_pins(so):
+    env = dict(os.environ, MGC_ORACLE_LIB=so)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    return r.returncode
+
+
+def test_every_planted_mistake_is_caught():
+    with tempfile.TemporaryDirectory() as tmp:
+        sos = [(m[0], _build_mutant(tmp, *m)) for m in MUTANTS]
+        with ThreadPoolExecutor(max_workers=6) as ex:
+            codes = list(ex.map(lambda x: _run_pins(x[1]), sos))
+    survivors = [name for (name, _), code in zip(sos, codes) if code == 0]
+    assert not survivors, f"pins did not catch: {survivors}"
