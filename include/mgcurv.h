@@ -1,0 +1,135 @@
+/*
+ * mgcurv.h -- C ABI of libmgcurv.so: multigrid minimisation of curvature
+ * energies (arXiv 2204.07921) on AMD Instinct MI355X (gfx950).
+ *
+ * The library minimises, for an image f on an H x W pixel grid,
+ *
+ *     F(u) = sum_pixels |kappa(u)| + alpha/2 (u - f)^2              (eq. MCM / eq. GCM)
+ *
+ * where kappa is the mean curvature div(grad u / sqrt(1 + |grad u|^2)) or the
+ * Gaussian curvature det(Hess u) / (1 + |grad u|^2)^2 of the image graph
+ * (Table 1), discretised with 3x3 central differences and replicated ghost
+ * pixels.  One V-cycle is the fine-to-coarse half cycle of Algorithm 3: for
+ * level j = 1..J (block side b_j = 2^(j-1), blocks clipped at the right and
+ * bottom edges), for each colour of the four-colour decomposition of
+ * Section 2.3 (colour of block (p, q) = 2 (p mod 2) + (q mod 2)), every block
+ * B of that colour receives u <- u + c_B chi_B with c_B the minimiser of the
+ * local energy F(u + c chi_B) (Section 2.2, the arg min of Algorithm 3).
+ * All c_B of one colour are computed from the state at the start of that
+ * colour.  The one-dimensional minimisation samples the bracket
+ * [f* - rho, f* + rho] (f* = mean of f - u over B, rho = sqrt(2 K(f*) / (alpha |B|)))
+ * at `samples` + 1 points, refines the best one by `bisections` bisection
+ * steps on the sign of the derivative, and keeps c = 0 unless the local
+ * energy does not rise.
+ *
+ * Conventions for every entry point:
+ *   - u and f are DEVICE pointers to contiguous row-major H x W arrays of
+ *     the context's state dtype (float or double).  The caller owns them.
+ *     u is read and written, f is only read; u must not alias f.
+ *   - Work is enqueued on the HIP stream given to mg_curv_init (NULL = the
+ *     null stream).  Calls that return a host value (energy, solve) block
+ *     until it is available; mg_curv_vcycle and mg_curv_sweep without a
+ *     requested energy return after enqueueing.
+ *   - Every entry point returns an mg_status and never throws.  A negative
+ *     status means the request was rejected or failed; on validation
+ *     failures u is not modified.  mg_curv_last_error describes the last
+ *     failure.
+ *   - A context is bound to one device and one stream; it is not thread-safe.
+ */
+#ifndef MGCURV_H
+#define MGCURV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_NOT_CONVERGED = 1,  /* warning: max_vcycles reached first; u holds the last iterate */
+    MG_E_INVALID = -1,     /* bad argument (null pointer, alpha <= 0, aliasing, bad option) */
+    MG_E_SHAPE = -2,       /* H or W < 2, or sizes beyond the supported range */
+    MG_E_DTYPE = -3,       /* state dtype not MG_F32 / MG_F64 */
+    MG_E_NOMEM = -4,       /* device allocation failed */
+    MG_E_DEVICE = -5,      /* no usable GPU, or a HIP call failed */
+    MG_E_NONFINITE = -6    /* the energy of the input state is NaN or infinite */
+} mg_status;
+
+typedef enum { MG_CURV_MEAN = 0, MG_CURV_GAUSS = 1 } mg_curv_kind;
+typedef enum { MG_F32 = 0, MG_F64 = 1 } mg_dtype;
+
+typedef struct {
+    int32_t height;        /* H >= 2 */
+    int32_t width;         /* W >= 2 */
+    double alpha;          /* data weight of eq. MCM / GCM, finite and > 0 */
+    int32_t curvature;     /* mg_curv_kind */
+    int32_t levels;        /* J >= 1; 0 selects ceil(log2(max(H, W))) */
+    int32_t state_dtype;   /* mg_dtype of u and f; the local minimisation always runs in FP64 */
+    int32_t fine_colours;  /* colours at the pixel level (b = 1): 4 (Section 2.3) or 9
+                              (3 x 3 pattern; pixels of one colour then share no ring pixel) */
+    int32_t samples;       /* M, even, 2..256 (default 16) */
+    int32_t bisections;    /* G, 0..64 (default 32) */
+} mg_curv_params;
+
+typedef struct mg_curv_ctx mg_curv_ctx;
+
+/* Fill *p with the defaults for an H x W image: alpha 20, mean curvature,
+ * levels 0 (automatic), float state, 4 fine colours, M = 16, G = 32. */
+void mg_curv_default_params(mg_curv_params *p, int32_t height, int32_t width);
+
+/* Validate *params, bind the current HIP device and `hip_stream`
+ * (a hipStream_t, may be NULL), and allocate the context's scratch (one
+ * H x W ping-pong image for the pixel level and the energy partial sums).
+ * On success *out receives a context the caller releases with
+ * mg_curv_destroy.  Errors: MG_E_INVALID / MG_E_SHAPE / MG_E_DTYPE for bad
+ * parameters, MG_E_DEVICE without a GPU, MG_E_NOMEM. */
+mg_status mg_curv_init(const mg_curv_params *params, void *hip_stream, mg_curv_ctx **out);
+
+/* One fine-to-coarse V-cycle of Algorithm 3 on u (in place).  If
+ * energy_after is non-null the call also evaluates F(u) afterwards and
+ * waits for it. */
+mg_status mg_curv_vcycle(mg_curv_ctx *ctx, void *u, const void *f, double *energy_after);
+
+/* Run V-cycles on u (in place, starting from the u given; pass a copy of f
+ * for the paper's usual start u0 = f) until the relative energy change
+ * |E_l - E_{l-1}| / |E_l| drops below rel_tol (the stopping rule of the
+ * paper's experiments, Section 4) or max_vcycles cycles have run.
+ * rel_tol <= 0 runs exactly max_vcycles cycles.  Outputs (each nullable):
+ * *vcycles_done, *final_energy, and energy_trace[0 .. done] (host array of
+ * at least max_vcycles + 1 doubles, E_0 = F(u) on entry).
+ * Returns MG_OK, MG_NOT_CONVERGED (rel_tol > 0 and the limit was hit) or an
+ * error; MG_E_NONFINITE if F(u) on entry is not finite (u untouched). */
+mg_status mg_curv_solve(mg_curv_ctx *ctx, void *u, const void *f, double rel_tol, int32_t max_vcycles,
+                        int32_t *vcycles_done, double *final_energy, double *energy_trace);
+
+/* F(u) of eq. MCM / GCM, accumulated in FP64 in a fixed order (the result is
+ * bitwise reproducible for a given size and launch). */
+mg_status mg_curv_energy(mg_curv_ctx *ctx, const void *u, const void *f, double *energy);
+
+/* One colour sweep of one level (1-based level, colour in [0, 4) or
+ * [0, 9) at level 1 with nine fine colours), in place on u.  This is the
+ * unit a V-cycle repeats; it is exported so a caller can inspect single
+ * steps.  Enqueued only. */
+mg_status mg_curv_sweep(mg_curv_ctx *ctx, void *u, const void *f, int32_t level, int32_t colour);
+
+/* All colours of one level (1-based), in place on u: the level-j part of one
+ * V-cycle of Algorithm 3 (4 colour sweeps, or 9 at level 1 with nine fine
+ * colours).  Enqueued only. */
+mg_status mg_curv_level(mg_curv_ctx *ctx, void *u, const void *f, int32_t level);
+
+/* Number of levels J the context uses (after resolving levels = 0). */
+int32_t mg_curv_levels(const mg_curv_ctx *ctx);
+
+/* Release the context (NULL is allowed).  Waits for its stream first. */
+void mg_curv_destroy(mg_curv_ctx *ctx);
+
+/* Text of the last error on this context, or of the calling thread's last
+ * failed mg_curv_init when ctx is NULL.  Never NULL. */
+const char *mg_curv_last_error(const mg_curv_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGCURV_H */

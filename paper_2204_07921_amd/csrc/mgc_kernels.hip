@@ -1,0 +1,347 @@
+// Colour-sweep and energy kernels for the multigrid curvature minimisation
+// (Algorithm 3 of arXiv 2204.07921) on gfx950.
+//
+// Level j has block side b = 2^(j-1).  A colour sweep updates every block of
+// one colour; blocks of one colour at b >= 2 never share a ring pixel, so they
+// run in parallel and update u in place.  At b = 1 same-colour pixels of the
+// four-colour map do share ring pixels, so the pixel level is two-phase: every
+// c is computed from the input state and written to a second image
+// (ping-pong), which makes the result independent of the schedule.
+//
+// The per-block work (sum of f - u, ring records, 1-D minimisation, apply)
+// runs on a lane group: 1 lane per pixel at b = 1, 16..64 lanes of one
+// wavefront for b <= 32, a whole workgroup (256 or 1024 lanes) for b >= 64.
+#include "mgc_device.h"
+#include "mgc_internal.h"
+
+namespace mgc {
+
+// ---------------------------------------------------------------------------
+// Pixel level (b = 1), two-phase.  One thread per cell of the colour pattern
+// (2x2 cells for four colours, 3x3 for nine); the thread solves the cell's
+// pixel of the active colour and copies the cell's other pixels.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, int NC>
+__global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                           const T* __restrict__ f, int H, int W, int colour,
+                                                           int cells_r, int cells_c, double alpha, int M, int G)
+{
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= cells_r * cells_c) return;
+    const int cr = cell / cells_c, cc = cell - cr * cells_c;
+    const int i = NC * cr + colour / NC;
+    const int j = NC * cc + colour % NC;
+
+    double cval = 0.0;
+    if (i < H && j < W) {
+        Ring rg[9];
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+                make_ring(uin, H, W, i + dy, j + dx, i, i + 1, j, j + 1, rg[(dy + 1) * 3 + dx + 1]);
+        const double fs = (double)f[(size_t)i * W + j] - (double)uin[(size_t)i * W + j];
+        auto K = [&](double c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc += abs_kappa<KIND>(rg[t], c);
+            return acc;
+        };
+        auto D = [&](double c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc += dabs_kappa<KIND>(rg[t], c);
+            return acc;
+        };
+        cval = local_solve(K, D, fs, alpha, M, G);
+    }
+    // write the cell
+#pragma unroll
+    for (int di = 0; di < NC; ++di) {
+        const int ii = NC * cr + di;
+        if (ii >= H) break;
+#pragma unroll
+        for (int dj = 0; dj < NC; ++dj) {
+            const int jj = NC * cc + dj;
+            if (jj >= W) break;
+            const size_t idx = (size_t)ii * W + jj;
+            T v = uin[idx];
+            if (ii == i && jj == j) v = (T)((double)v + cval);
+            uout[idx] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ring candidates of block rows [r0, r1) x cols [c0, c1): the pixels of the box
+// [r0 - 1, r1] x [c0 - 1, c1] at distance <= 1 from the block's boundary.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int band_count(int h, int w)
+{
+    if (h <= 2 || w <= 2) return (h + 2) * (w + 2);
+    return 4 * (w + 2) + 4 * (h - 2);
+}
+
+__device__ __forceinline__ void band_pixel(int k, int r0, int r1, int c0, int c1, int& i, int& j)
+{
+    const int h = r1 - r0, w = c1 - c0, bw = w + 2;
+    if (h <= 2 || w <= 2) { i = r0 - 1 + k / bw; j = c0 - 1 + k % bw; return; }
+    const int top = 2 * bw, mid = 4 * (h - 2);
+    if (k < top) { i = r0 - 1 + k / bw; j = c0 - 1 + k % bw; return; }
+    k -= top;
+    if (k < mid) {
+        i = r0 + 1 + (k >> 2);
+        const int m = k & 3;
+        j = (m == 0) ? c0 - 1 : (m == 1) ? c0 : (m == 2) ? c1 - 1 : c1;
+        return;
+    }
+    k -= mid;
+    i = r1 - 1 + k / bw;
+    j = c0 - 1 + k % bw;
+}
+
+// ---------------------------------------------------------------------------
+// Block levels (b >= 2), in place.  GROUP lanes per block; each lane keeps RPL
+// ring records in registers (RPL = 0: records are rebuilt from memory at every
+// evaluation, for blocks whose ring does not fit in registers).
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, int GROUP, int RPL, class GSum>
+__device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restrict__ f, int H, int W,
+                                            int r0, int r1, int c0, int c1, int lane, double alpha, int M, int G,
+                                            const GSum& gsum)
+{
+    const int h = r1 - r0, w = c1 - c0;
+    // r = sum over B of (f - u)
+    double r = 0.0;
+    for (int k = lane; k < h * w; k += GROUP) {
+        const int i = r0 + k / w, j = c0 + k % w;
+        const size_t idx = (size_t)i * W + j;
+        r += (double)f[idx] - (double)u[idx];
+    }
+    r = gsum(r);
+    const double s = (double)h * (double)w;
+    const double fs = r / s;
+    const int ncand = band_count(h, w);
+
+    double cval;
+    if (RPL > 0) {
+        Ring rg[RPL > 0 ? RPL : 1];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+            const int k = lane + t * GROUP;
+            if (k < ncand) {
+                int i, j;
+                band_pixel(k, r0, r1, c0, c1, i, j);
+                make_ring(u, H, W, i, j, r0, r1, c0, c1, rg[t]);
+            } else {
+                zero_ring(rg[t]);
+            }
+        }
+        auto K = [&](double c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) acc += abs_kappa<KIND>(rg[t], c);
+            return gsum(acc);
+        };
+        auto D = [&](double c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) acc += dabs_kappa<KIND>(rg[t], c);
+            return gsum(acc);
+        };
+        cval = local_solve(K, D, fs, alpha * s, M, G);
+    } else {
+        auto K = [&](double c) {
+            double acc = 0.0;
+            for (int k = lane; k < ncand; k += GROUP) {
+                int i, j;
+                Ring rr;
+                band_pixel(k, r0, r1, c0, c1, i, j);
+                make_ring(u, H, W, i, j, r0, r1, c0, c1, rr);
+                acc += abs_kappa<KIND>(rr, c);
+            }
+            return gsum(acc);
+        };
+        auto D = [&](double c) {
+            double acc = 0.0;
+            for (int k = lane; k < ncand; k += GROUP) {
+                int i, j;
+                Ring rr;
+                band_pixel(k, r0, r1, c0, c1, i, j);
+                make_ring(u, H, W, i, j, r0, r1, c0, c1, rr);
+                acc += dabs_kappa<KIND>(rr, c);
+            }
+            return gsum(acc);
+        };
+        cval = local_solve(K, D, fs, alpha * s, M, G);
+    }
+    if (cval != 0.0) {
+        for (int k = lane; k < h * w; k += GROUP) {
+            const int i = r0 + k / w, j = c0 + k % w;
+            const size_t idx = (size_t)i * W + j;
+            u[idx] = (T)((double)u[idx] + cval);
+        }
+    }
+}
+
+// Blocks of colour (pr, pc) at side b: block (p, q) = (2 bi + pr, 2 bj + pc), bi < nbr, bj < nbc.
+template <typename T, int KIND, int GROUP, int RPL>
+__global__ __launch_bounds__(GROUP >= 256 ? GROUP : 256) void sweep_blocks_kernel(
+    T* __restrict__ u, const T* __restrict__ f, int H, int W, int b, int pr, int pc, int nbr, int nbc,
+    double alpha, int M, int G)
+{
+    if constexpr (GROUP <= 64) {
+        const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
+        const int lane = threadIdx.x & (GROUP - 1);
+        if (gid >= nbr * nbc) return;  // whole groups exit together
+        const int bi = gid / nbc, bj = gid - bi * nbc;
+        const int r0 = (2 * bi + pr) * b, c0 = (2 * bj + pc) * b;
+        const int r1 = min(r0 + b, H), c1 = min(c0 + b, W);
+        solve_block<T, KIND, GROUP, RPL>(u, f, H, W, r0, r1, c0, c1, lane, alpha, M, G, WaveSum<GROUP>());
+    } else {
+        __shared__ double lds[2 * (GROUP / 64)];
+        const int gid = blockIdx.x;
+        const int bi = gid / nbc, bj = gid - bi * nbc;
+        const int r0 = (2 * bi + pr) * b, c0 = (2 * bj + pc) * b;
+        const int r1 = min(r0 + b, H), c1 = min(c0 + b, W);
+        BlockSum<GROUP> gs{lds, 0};
+        solve_block<T, KIND, GROUP, RPL>(u, f, H, W, r0, r1, c0, c1, threadIdx.x, alpha, M, G, gs);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Energy F(u) = sum |kappa| + alpha/2 (u - f)^2 in FP64: fixed-size grid of
+// partial sums, then one workgroup adds the partials in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void energy_partial_kernel(const T* __restrict__ u, const T* __restrict__ f,
+                                                             int H, int W, double alpha, double* __restrict__ partials)
+{
+    __shared__ double lds[4];
+    const size_t n = (size_t)H * W;
+    double acc = 0.0;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p / W), j = (int)(p - (size_t)i * W);
+        const double d = (double)u[p] - (double)f[p];
+        acc += abs_kappa_at<KIND>(u, H, W, i, j) + 0.5 * alpha * d * d;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partials, int n,
+                                                           double* __restrict__ out)
+{
+    __shared__ double lds[4];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) acc += partials[k];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+static hipError_t launch_pixels_t(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int nc)
+{
+    const int cells_r = (L.H + nc - 1) / nc, cells_c = (L.W + nc - 1) / nc;
+    const int n = cells_r * cells_c;
+    dim3 grid((n + 255) / 256), block(256);
+    if (nc == 3)
+        hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, 3>), grid, block, 0, L.stream, (const T*)uin, (T*)uout,
+                           (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
+    else
+        hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, 2>), grid, block, 0, L.stream, (const T*)uin, (T*)uout,
+                           (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours)
+{
+    // nine colours use 3x3 cells, four colours 2x2 cells
+    const int nc = (ncolours == 9) ? 3 : 2;
+    if (L.f64) return L.kind ? launch_pixels_t<double, 1>(L, uin, uout, f, colour, nc)
+                             : launch_pixels_t<double, 0>(L, uin, uout, f, colour, nc);
+    return L.kind ? launch_pixels_t<float, 1>(L, uin, uout, f, colour, nc)
+                  : launch_pixels_t<float, 0>(L, uin, uout, f, colour, nc);
+}
+
+template <typename T, int KIND, int GROUP, int RPL>
+static hipError_t launch_blocks_cfg(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr, int nbc)
+{
+    const int groups = nbr * nbc;
+    if (groups == 0) return hipSuccess;
+    dim3 grid, block;
+    if (GROUP <= 64) {
+        block = dim3(256);
+        grid = dim3((unsigned)(((size_t)groups * GROUP + 255) / 256));
+    } else {
+        block = dim3(GROUP);
+        grid = dim3(groups);
+    }
+    hipLaunchKernelGGL((sweep_blocks_kernel<T, KIND, GROUP, RPL>), grid, block, 0, L.stream, (T*)u, (const T*)f,
+                       L.H, L.W, b, pr, pc, nbr, nbc, L.alpha, L.M, L.G);
+    return hipGetLastError();
+}
+
+template <typename T, int KIND>
+static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr, int nbc)
+{
+    // ring size of an unclipped block is 8b
+    switch (b) {
+    case 2: return launch_blocks_cfg<T, KIND, 16, 1>(L, u, f, b, pr, pc, nbr, nbc);
+    case 4: return launch_blocks_cfg<T, KIND, 32, 1>(L, u, f, b, pr, pc, nbr, nbc);
+    case 8: return launch_blocks_cfg<T, KIND, 64, 1>(L, u, f, b, pr, pc, nbr, nbc);
+    case 16: return launch_blocks_cfg<T, KIND, 64, 2>(L, u, f, b, pr, pc, nbr, nbc);
+    case 32: return launch_blocks_cfg<T, KIND, 64, 4>(L, u, f, b, pr, pc, nbr, nbc);
+    case 64: return launch_blocks_cfg<T, KIND, 256, 2>(L, u, f, b, pr, pc, nbr, nbc);
+    case 128: return launch_blocks_cfg<T, KIND, 256, 4>(L, u, f, b, pr, pc, nbr, nbc);
+    case 256: return launch_blocks_cfg<T, KIND, 1024, 2>(L, u, f, b, pr, pc, nbr, nbc);
+    case 512: return launch_blocks_cfg<T, KIND, 1024, 4>(L, u, f, b, pr, pc, nbr, nbc);
+    default: return launch_blocks_cfg<T, KIND, 1024, 0>(L, u, f, b, pr, pc, nbr, nbc);
+    }
+}
+
+hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour)
+{
+    const int pr = colour >> 1, pc = colour & 1;
+    const int mj = (L.H + b - 1) / b, nj = (L.W + b - 1) / b;
+    const int nbr = (mj - pr + 1) / 2, nbc = (nj - pc + 1) / 2;
+    if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc)
+                             : launch_blocks_t<double, 0>(L, u, f, b, pr, pc, nbr, nbc);
+    return L.kind ? launch_blocks_t<float, 1>(L, u, f, b, pr, pc, nbr, nbc)
+                  : launch_blocks_t<float, 0>(L, u, f, b, pr, pc, nbr, nbc);
+}
+
+int energy_partials_count(int H, int W)
+{
+    const size_t n = (size_t)H * W;
+    size_t g = (n + 255) / 256;
+    return (int)(g < 2048 ? g : 2048);
+}
+
+hipError_t launch_energy(const LaunchCtx& L, const void* u, const void* f, double* partials, double* out)
+{
+    const int np = energy_partials_count(L.H, L.W);
+    dim3 grid(np), block(256);
+    if (L.f64) {
+        if (L.kind) hipLaunchKernelGGL((energy_partial_kernel<double, 1>), grid, block, 0, L.stream, (const double*)u, (const double*)f, L.H, L.W, L.alpha, partials);
+        else hipLaunchKernelGGL((energy_partial_kernel<double, 0>), grid, block, 0, L.stream, (const double*)u, (const double*)f, L.H, L.W, L.alpha, partials);
+    } else {
+        if (L.kind) hipLaunchKernelGGL((energy_partial_kernel<float, 1>), grid, block, 0, L.stream, (const float*)u, (const float*)f, L.H, L.W, L.alpha, partials);
+        else hipLaunchKernelGGL((energy_partial_kernel<float, 0>), grid, block, 0, L.stream, (const float*)u, (const float*)f, L.H, L.W, L.alpha, partials);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, L.stream, partials, np, out);
+    return hipGetLastError();
+}
+
+}  // namespace mgc

@@ -1,0 +1,302 @@
+// Host runtime of libmgcurv.so: parameter validation, context and scratch
+// ownership, the V-cycle and solve drivers of Algorithm 3, and the C ABI
+// declared in include/mgcurv.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/mgcurv.h"
+#include "mgc_internal.h"
+
+struct mg_curv_ctx {
+    mg_curv_params P;
+    int J;
+    int device;
+    hipStream_t stream;
+    void* pingpong;        // H x W state-dtype image for the two-phase pixel level
+    double* partials;      // energy partial sums
+    double* energy_dev;    // one double
+    double* energy_host;   // pinned host double
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+mg_status fail(mg_curv_ctx* ctx, mg_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf; else g_init_error = buf;
+    return st;
+}
+
+mg_status hip_fail(mg_curv_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, MG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int auto_levels(int H, int W)
+{
+    int m = H > W ? H : W, J = 0;
+    while ((1 << J) < m) ++J;   // ceil(log2(max(H, W)))
+    return J < 1 ? 1 : J;
+}
+
+size_t state_bytes(const mg_curv_ctx* c)
+{
+    return (size_t)c->P.height * c->P.width * (c->P.state_dtype == MG_F64 ? 8 : 4);
+}
+
+mgc::LaunchCtx launch_ctx(const mg_curv_ctx* c)
+{
+    mgc::LaunchCtx L;
+    L.stream = c->stream;
+    L.H = c->P.height;
+    L.W = c->P.width;
+    L.alpha = c->P.alpha;
+    L.kind = c->P.curvature;
+    L.f64 = c->P.state_dtype == MG_F64;
+    L.M = c->P.samples;
+    L.G = c->P.bisections;
+    return L;
+}
+
+int colours_at(const mg_curv_ctx* c, int level) { return (level == 1 && c->P.fine_colours == 9) ? 9 : 4; }
+
+mg_status check_buffers(mg_curv_ctx* ctx, const void* u, const void* f)
+{
+    if (!ctx) return MG_E_INVALID;
+    if (!u || !f) return fail(ctx, MG_E_INVALID, "u and f must be non-null device pointers");
+    const size_t n = state_bytes(ctx);
+    const char* a = (const char*)u;
+    const char* b = (const char*)f;
+    if (a < b + n && b < a + n) return fail(ctx, MG_E_INVALID, "u must not overlap f");
+    return MG_OK;
+}
+
+// One colour sweep of one level, on u in place.
+mg_status sweep(mg_curv_ctx* ctx, void* u, const void* f, int level, int colour)
+{
+    const mgc::LaunchCtx L = launch_ctx(ctx);
+    hipError_t e;
+    if (level == 1) {
+        e = mgc::launch_sweep_pixels(L, u, ctx->pingpong, f, colour, colours_at(ctx, 1));
+        if (e != hipSuccess) return hip_fail(ctx, e, "pixel sweep launch");
+        e = hipMemcpyAsync(u, ctx->pingpong, state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "pixel sweep copy");
+        return MG_OK;
+    }
+    e = mgc::launch_sweep_blocks(L, u, f, 1 << (level - 1), colour);
+    if (e != hipSuccess) return hip_fail(ctx, e, "block sweep launch");
+    return MG_OK;
+}
+
+// All colours of one level.  The pixel level ping-pongs between u and the
+// scratch image (two-phase update); with an odd number of colours the result
+// is copied back into u.
+mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level)
+{
+    const mgc::LaunchCtx L = launch_ctx(ctx);
+    hipError_t e;
+    if (level == 1) {
+        const int nc = colours_at(ctx, 1);
+        void* cur = u;
+        void* nxt = ctx->pingpong;
+        for (int colour = 0; colour < nc; ++colour) {
+            e = mgc::launch_sweep_pixels(L, cur, nxt, f, colour, nc);
+            if (e != hipSuccess) return hip_fail(ctx, e, "pixel sweep launch");
+            void* t = cur; cur = nxt; nxt = t;
+        }
+        if (cur != u) {
+            e = hipMemcpyAsync(u, cur, state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "pixel level copy");
+        }
+        return MG_OK;
+    }
+    for (int colour = 0; colour < 4; ++colour) {
+        e = mgc::launch_sweep_blocks(L, u, f, 1 << (level - 1), colour);
+        if (e != hipSuccess) return hip_fail(ctx, e, "block sweep launch");
+    }
+    return MG_OK;
+}
+
+// All levels fine to coarse, all colours (one outer iteration of Algorithm 3).
+mg_status vcycle(mg_curv_ctx* ctx, void* u, const void* f)
+{
+    for (int level = 1; level <= ctx->J; ++level) {
+        mg_status st = level_sweeps(ctx, u, f, level);
+        if (st != MG_OK) return st;
+    }
+    return MG_OK;
+}
+
+mg_status energy(mg_curv_ctx* ctx, const void* u, const void* f, double* out)
+{
+    const mgc::LaunchCtx L = launch_ctx(ctx);
+    hipError_t e = mgc::launch_energy(L, u, f, ctx->partials, ctx->energy_dev);
+    if (e != hipSuccess) return hip_fail(ctx, e, "energy launch");
+    e = hipMemcpyAsync(ctx->energy_host, ctx->energy_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "energy copy");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+    *out = *ctx->energy_host;
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mg_curv_default_params(mg_curv_params* p, int32_t height, int32_t width)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->height = height;
+    p->width = width;
+    p->alpha = 20.0;
+    p->curvature = MG_CURV_MEAN;
+    p->levels = 0;
+    p->state_dtype = MG_F32;
+    p->fine_colours = 4;
+    p->samples = 16;
+    p->bisections = 32;
+}
+
+mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_ctx** out)
+{
+    if (!params || !out) return fail(nullptr, MG_E_INVALID, "params and out must be non-null");
+    *out = nullptr;
+    const mg_curv_params& p = *params;
+    if (p.height < 2 || p.width < 2) return fail(nullptr, MG_E_SHAPE, "height and width must be >= 2 (got %d x %d)", p.height, p.width);
+    if ((int64_t)p.height * p.width > ((int64_t)1 << 31) - 1)
+        return fail(nullptr, MG_E_SHAPE, "image larger than 2^31 - 1 pixels");
+    if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return fail(nullptr, MG_E_INVALID, "alpha must be finite and > 0");
+    if (p.curvature != MG_CURV_MEAN && p.curvature != MG_CURV_GAUSS) return fail(nullptr, MG_E_INVALID, "curvature must be 0 (mean) or 1 (Gaussian)");
+    if (p.state_dtype != MG_F32 && p.state_dtype != MG_F64) return fail(nullptr, MG_E_DTYPE, "state_dtype must be MG_F32 or MG_F64");
+    if (p.fine_colours != 4 && p.fine_colours != 9) return fail(nullptr, MG_E_INVALID, "fine_colours must be 4 or 9");
+    if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return fail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");
+    if (p.bisections < 0 || p.bisections > 64) return fail(nullptr, MG_E_INVALID, "bisections must be in [0, 64]");
+    const int Jmax = auto_levels(p.height, p.width) + 1;
+    if (p.levels < 0 || p.levels > Jmax) return fail(nullptr, MG_E_INVALID, "levels must be in [0, %d]", Jmax);
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(nullptr, MG_E_DEVICE, "no HIP device available");
+    mg_curv_ctx* c = new (std::nothrow) mg_curv_ctx();
+    if (!c) return fail(nullptr, MG_E_NOMEM, "host allocation failed");
+    c->P = p;
+    c->J = p.levels > 0 ? p.levels : auto_levels(p.height, p.width);
+    c->stream = (hipStream_t)hip_stream;
+    c->pingpong = nullptr;
+    c->partials = nullptr;
+    c->energy_dev = nullptr;
+    c->energy_host = nullptr;
+    (void)hipGetDevice(&c->device);
+    const size_t nb = state_bytes(c);
+    const int np = mgc::energy_partials_count(p.height, p.width);
+    if (hipMalloc(&c->pingpong, nb) != hipSuccess || hipMalloc((void**)&c->partials, sizeof(double) * np) != hipSuccess ||
+        hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        mg_curv_destroy(c);
+        (void)hipGetLastError();
+        return fail(nullptr, MG_E_NOMEM, "device allocation of %zu bytes failed", nb);
+    }
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_curv_vcycle(mg_curv_ctx* ctx, void* u, const void* f, double* energy_after)
+{
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    st = vcycle(ctx, u, f);
+    if (st != MG_OK || !energy_after) return st;
+    return energy(ctx, u, f, energy_after);
+}
+
+mg_status mg_curv_sweep(mg_curv_ctx* ctx, void* u, const void* f, int32_t level, int32_t colour)
+{
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    if (level < 1 || level > ctx->J) return fail(ctx, MG_E_INVALID, "level must be in [1, %d]", ctx->J);
+    if (colour < 0 || colour >= colours_at(ctx, level)) return fail(ctx, MG_E_INVALID, "colour out of range for level %d", level);
+    return sweep(ctx, u, f, level, colour);
+}
+
+mg_status mg_curv_level(mg_curv_ctx* ctx, void* u, const void* f, int32_t level)
+{
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    if (level < 1 || level > ctx->J) return fail(ctx, MG_E_INVALID, "level must be in [1, %d]", ctx->J);
+    return level_sweeps(ctx, u, f, level);
+}
+
+mg_status mg_curv_energy(mg_curv_ctx* ctx, const void* u, const void* f, double* out)
+{
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    if (!out) return fail(ctx, MG_E_INVALID, "energy output must be non-null");
+    return energy(ctx, u, f, out);
+}
+
+mg_status mg_curv_solve(mg_curv_ctx* ctx, void* u, const void* f, double rel_tol, int32_t max_vcycles,
+                        int32_t* vcycles_done, double* final_energy, double* energy_trace)
+{
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    if (max_vcycles < 0) return fail(ctx, MG_E_INVALID, "max_vcycles must be >= 0");
+    if (!std::isfinite(rel_tol)) return fail(ctx, MG_E_INVALID, "rel_tol must be finite");
+    double e_prev;
+    st = energy(ctx, u, f, &e_prev);
+    if (st != MG_OK) return st;
+    if (!std::isfinite(e_prev)) return fail(ctx, MG_E_NONFINITE, "energy of the initial state is not finite");
+    if (energy_trace) energy_trace[0] = e_prev;
+    int done = 0;
+    bool converged = false;
+    double e = e_prev;
+    while (done < max_vcycles) {
+        st = vcycle(ctx, u, f);
+        if (st != MG_OK) return st;
+        st = energy(ctx, u, f, &e);
+        if (st != MG_OK) return st;
+        ++done;
+        if (energy_trace) energy_trace[done] = e;
+        if (!std::isfinite(e)) return fail(ctx, MG_E_NONFINITE, "energy became non-finite after V-cycle %d", done);
+        if (rel_tol > 0.0 && (e == e_prev || std::fabs(e - e_prev) < rel_tol * std::fabs(e))) { converged = true; break; }
+        e_prev = e;
+    }
+    if (vcycles_done) *vcycles_done = done;
+    if (final_energy) *final_energy = e;
+    return (rel_tol > 0.0 && !converged) ? MG_NOT_CONVERGED : MG_OK;
+}
+
+int32_t mg_curv_levels(const mg_curv_ctx* ctx) { return ctx ? ctx->J : 0; }
+
+void mg_curv_destroy(mg_curv_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream || ctx->pingpong) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pingpong) (void)hipFree(ctx->pingpong);
+    if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
+    if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
+    delete ctx;
+}
+
+const char* mg_curv_last_error(const mg_curv_ctx* ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_init_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+"""ctypes binding of libmgcurv.so (include/mgcurv.h).  Argument marshalling only.
+
+Every function takes torch CUDA (HIP) tensors and passes their device pointers
+and the current HIP stream to the library; no step of the method runs here.
+If the library cannot be loaded the import fails loudly: there is no CPU or
+PyTorch fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgcurv.so")
+
+MG_OK, MG_NOT_CONVERGED = 0, 1
+MG_CURV_MEAN, MG_CURV_GAUSS = 0, 1
+MG_F32, MG_F64 = 0, 1
+STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_E_INVALID", -2: "MG_E_SHAPE",
+                -3: "MG_E_DTYPE", -4: "MG_E_NOMEM", -5: "MG_E_DEVICE", -6: "MG_E_NONFINITE"}
+
+
+class MgCurvParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
+                ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
+                ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32)]
+
+
+class MgCurvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER(MgCurvParams)
+    vp, cvp = C.c_void_p, C.c_void_p
+    L.mg_curv_default_params.restype = None
+    L.mg_curv_default_params.argtypes = [P, C.c_int32, C.c_int32]
+    L.mg_curv_init.restype = C.c_int
+    L.mg_curv_init.argtypes = [P, vp, C.POINTER(vp)]
+    L.mg_curv_vcycle.restype = C.c_int
+    L.mg_curv_vcycle.argtypes = [vp, vp, cvp, C.POINTER(C.c_double)]
+    L.mg_curv_solve.restype = C.c_int
+    L.mg_curv_solve.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.mg_curv_energy.restype = C.c_int
+    L.mg_curv_energy.argtypes = [vp, cvp, cvp, C.POINTER(C.c_double)]
+    L.mg_curv_sweep.restype = C.c_int
+    L.mg_curv_sweep.argtypes = [vp, vp, cvp, C.c_int32, C.c_int32]
+    L.mg_curv_level.restype = C.c_int
+    L.mg_curv_level.argtypes = [vp, vp, cvp, C.c_int32]
+    L.mg_curv_levels.restype = C.c_int32
+    L.mg_curv_levels.argtypes = [vp]
+    L.mg_curv_destroy.restype = None
+    L.mg_curv_destroy.argtypes = [vp]
+    L.mg_curv_last_error.restype = C.c_char_p
+    L.mg_curv_last_error.argtypes = [vp]
+    return L
+
+
+lib = _load()
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check(status: int, ctx=None) -> int:
+    if status < 0:
+        raise MgCurvError(status, lib.mg_curv_last_error(ctx).decode())
+    return status
+
+
+def default_params(height: int, width: int, **kw) -> MgCurvParams:
+    p = MgCurvParams()
+    lib.mg_curv_default_params(C.byref(p), height, width)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return MG_F32
+    if t.dtype == torch.float64:
+        return MG_F64
+    raise TypeError(f"state tensors must be float32 or float64, got {t.dtype}")
+
+
+def _tensor_ptr(t: torch.Tensor, p: MgCurvParams, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != (p.height, p.width):
+        raise ValueError(f"{name} must have shape {(p.height, p.width)}, got {tuple(t.shape)}")
+    if _dtype_code(t) != p.state_dtype:
+        raise TypeError(f"{name} dtype does not match the context's state dtype")
+    return t.data_ptr()
+
+
+# --- functions with the ABI's names --------------------------------------------------
+
+def mg_curv_init(params: MgCurvParams, stream=None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _check(lib.mg_curv_init(C.byref(params), C.c_void_p(_stream_handle(stream)), C.byref(ctx)))
+    return ctx
+
+
+def mg_curv_vcycle(ctx, params, u, f, want_energy: bool = False):
+    e = C.c_double()
+    _check(lib.mg_curv_vcycle(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"),
+                              C.byref(e) if want_energy else None), ctx)
+    return e.value if want_energy else None
+
+
+def mg_curv_solve(ctx, params, u, f, rel_tol: float = 1e-6, max_vcycles: int = 1000, trace: bool = False):
+    done = C.c_int32()
+    fin = C.c_double()
+    buf = (C.c_double * (max_vcycles + 1))() if trace else None
+    st = _check(lib.mg_curv_solve(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), rel_tol,
+                                  max_vcycles, C.byref(done), C.byref(fin), buf), ctx)
+    out = {"status": st, "vcycles": done.value, "energy": fin.value}
+    if trace:
+        out["trace"] = [buf[k] for k in range(done.value + 1)]
+    return out
+
+
+def mg_curv_energy(ctx, params, u, f) -> float:
+    e = C.c_double()
+    _check(lib.mg_curv_energy(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), C.byref(e)), ctx)
+    return e.value
+
+
+def mg_curv_sweep(ctx, params, u, f, level: int, colour: int) -> None:
+    _check(lib.mg_curv_sweep(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), level, colour), ctx)
+
+
+def mg_curv_level(ctx, params, u, f, level: int) -> None:
+    _check(lib.mg_curv_level(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), level), ctx)
+
+
+def mg_curv_destroy(ctx) -> None:
+    lib.mg_curv_destroy(ctx)
+
+
+# --- convenience object ----------------------------------------------------------
+
+class Solver:
+    """One context: fixed image size, alpha, curvature kind, dtype and stream."""
+
+    def __init__(self, height: int, width: int, alpha: float = 20.0, kind: int = MG_CURV_MEAN,
+                 levels: int = 0, dtype=torch.float32, fine_colours: int = 4, samples: int = 16,
+                 bisections: int = 32, stream=None):
+        self.params = default_params(height, width, alpha=float(alpha), curvature=int(kind), levels=int(levels),
+                                     state_dtype=MG_F64 if dtype == torch.float64 else MG_F32,
+                                     fine_colours=int(fine_colours), samples=int(samples),
+                                     bisections=int(bisections))
+        self.dtype = dtype
+        self.ctx = mg_curv_init(self.params, stream)
+        self.levels = lib.mg_curv_levels(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            mg_curv_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vcycle(self, u, f, want_energy=False):
+        return mg_curv_vcycle(self.ctx, self.params, u, f, want_energy)
+
+    def solve(self, u, f, rel_tol=1e-6, max_vcycles=1000, trace=False):
+        return mg_curv_solve(self.ctx, self.params, u, f, rel_tol, max_vcycles, trace)
+
+    def energy(self, u, f):
+        return mg_curv_energy(self.ctx, self.params, u, f)
+
+    def sweep(self, u, f, level, colour):
+        return mg_curv_sweep(self.ctx, self.params, u, f, level, colour)
+
+    def level(self, u, f, level):
+        return mg_curv_level(self.ctx, self.params, u, f, level)

@@ -1,0 +1,97 @@
+"""C-ABI contract of libmgcurv.so on a machine without a GPU: the library loads,
+exports every entry point include/mgcurv.h declares, validates parameters before
+touching a device and reports MG_E_DEVICE when no GPU is present.  No compute
+call is made here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgcurv.h")
+LIB = os.path.join(ROOT, "paper_2204_07921_amd", "libmgcurv.so")
+
+
+class Params(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
+                ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
+                ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2204_07921_amd import build
+        build.build()
+    L = C.CDLL(LIB)
+    L.mg_curv_init.restype = C.c_int
+    L.mg_curv_init.argtypes = [C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p)]
+    L.mg_curv_last_error.restype = C.c_char_p
+    L.mg_curv_last_error.argtypes = [C.c_void_p]
+    L.mg_curv_default_params.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32]
+    for name in ("mg_curv_vcycle", "mg_curv_energy", "mg_curv_sweep", "mg_curv_solve", "mg_curv_level"):
+        getattr(L, name).restype = C.c_int
+    return L
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    names = declared_symbols()
+    for required in ("mg_curv_init", "mg_curv_vcycle", "mg_curv_solve", "mg_curv_energy",
+                     "mg_curv_destroy", "mg_curv_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_params_struct_layout(lib):
+    assert C.sizeof(Params) == 40
+    p = Params()
+    lib.mg_curv_default_params(C.byref(p), 64, 48)
+    assert (p.height, p.width, p.alpha, p.curvature, p.levels, p.state_dtype) == (64, 48, 20.0, 0, 0, 0)
+    assert (p.fine_colours, p.samples, p.bisections) == (4, 16, 32)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("height", 1, -2), ("width", 0, -2), ("alpha", 0.0, -1), ("alpha", float("nan"), -1),
+    ("alpha", float("inf"), -1), ("curvature", 2, -1), ("state_dtype", 7, -3), ("fine_colours", 5, -1),
+    ("samples", 3, -1), ("samples", 0, -1), ("bisections", -1, -1), ("bisections", 65, -1), ("levels", 99, -1),
+])
+def test_invalid_params_rejected_before_device(lib, field, value, status):
+    p = Params()
+    lib.mg_curv_default_params(C.byref(p), 64, 64)
+    setattr(p, field, value)
+    ctx = C.c_void_p(1234)
+    st = lib.mg_curv_init(C.byref(p), None, C.byref(ctx))
+    assert st == status
+    assert not ctx.value
+    assert lib.mg_curv_last_error(None)
+
+
+def test_null_arguments(lib):
+    ctx = C.c_void_p()
+    assert lib.mg_curv_init(None, None, C.byref(ctx)) == -1
+    assert lib.mg_curv_vcycle(None, None, None, None) == -1
+    assert lib.mg_curv_energy(None, None, None, None) == -1
+    assert lib.mg_curv_sweep(None, None, None, 1, 0) == -1
+    assert lib.mg_curv_level(None, None, None, 1) == -1
+    lib.mg_curv_destroy(None)
+
+
+def test_no_device_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = Params()
+    lib.mg_curv_default_params(C.byref(p), 64, 64)
+    ctx = C.c_void_p()
+    assert lib.mg_curv_init(C.byref(p), None, C.byref(ctx)) == -5
+    assert b"device" in lib.mg_curv_last_error(None).lower()

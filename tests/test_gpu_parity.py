@@ -1,0 +1,322 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances, derived from the arithmetic:
+  * FP64 state: the two sides differ only in summation order and in rounding
+    of algebraically equal expressions (about 1e-16 relative per term); the
+    local searches take the same branches unless a derivative is within
+    rounding of zero, so u agrees to <= 1e-10 after 20 V-cycles (the target
+    stated for the FP64 mode) and a single sweep to <= 1e-12.
+  * FP32 state: both sides run the local solve in FP64 on the same float
+    inputs and round the result to float, so they agree to an ulp or two
+    (<= 1e-6 at unit scale) with the oracle's float-state option; against the
+    pure FP64 oracle the target is <= 1e-4.
+  * Energy: two summation orders of N non-negative terms differ by at most
+    about 2 N eps relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import noisy_image
+
+pytestmark = pytest.mark.gpu
+
+THREADS = 8
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2204_07921_amd import mgcurv
+    return mgcurv
+
+
+def dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _f_and_u(h, w, seed, sigma, dtype, perturb=0.0):
+    f, _ = noisy_image(h, w, seed, sigma, dtype=np.float32 if dtype == torch.float32 else np.float64)
+    f = f.astype(np.float64)
+    u = f.copy()
+    if perturb:
+        rng = np.random.default_rng(seed + 77)
+        u = u + perturb * rng.standard_normal(u.shape)
+        if dtype == torch.float32:
+            u = u.astype(np.float32).astype(np.float64)
+    return f, u
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("shape", [(2, 2), (37, 53), (64, 64), (1024, 1024)])
+def test_energy_parity(mg, orc, dtype, kind, shape):
+    h, w = shape
+    _case(f"energy {shape} kind={kind} {dtype}")
+    f, u = _f_and_u(h, w, 3, 0.1, dtype, perturb=0.05)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype)
+    e_gpu = s.energy(dev(u, dtype), dev(f, dtype))
+    e_orc = orc.oracle.energy(kind, u, f, 20.0)
+    assert abs(e_gpu - e_orc) <= 2.2e-16 * max(h * w, 8) * abs(e_orc), (e_gpu, e_orc)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("colours", [4, 9])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_single_sweep_parity_every_level(mg, orc, kind, colours, dtype):
+    """Every level and colour of a ragged image (clipped blocks at every level)."""
+    h, w = 45, 37
+    f, u0 = _f_and_u(h, w, 5, 0.1, dtype, perturb=0.05)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype, fine_colours=colours)
+    o = orc.Oracle(h, w, 20.0, kind, fine_colours=colours, round_f32=(dtype == torch.float32), threads=THREADS)
+    assert s.levels == o.levels
+    fd = dev(f, dtype)
+    for level in range(1, o.levels + 1):
+        for colour in range(o.num_colours(level)):
+            _case(f"sweep kind={kind} colours={colours} {dtype} level={level} colour={colour}")
+            ug = dev(u0, dtype)
+            s.sweep(ug, fd, level, colour)
+            worst, n_equal = _check_sweep_against_oracle(o, f, u0, host(ug), level, colour,
+                                                         fp64=dtype == torch.float64)
+            assert n_equal <= 1, (level, colour, n_equal)
+
+
+def _blocks_of(o, level, colour):
+    m, n = o.grid(level)
+    return [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
+
+
+def _check_sweep_against_oracle(o, f, before, after, level, colour, fp64=True):
+    """Teacher-forced parity of one colour sweep: the oracle solves every block of the colour from the
+    GPU's own input state.  A block passes if its correction matches to 1e-10 (FP64 state; in FP32 the
+    rounded block values must match), or, where the arg-min is ill-conditioned (a minimum on a kink of
+    |kappa| with a tiny slope), if the GPU's correction reaches the same local-energy minimum
+    (oracle's Delta at the GPU's c within 1e-12 (1 + V0) of the oracle's own).  Returns
+    (max |dc|, number of blocks that needed the equal-minimum criterion)."""
+    worst, n_equal = 0.0, 0
+    for p, q in _blocks_of(o, level, colour):
+        bnd = o.block_bounds(level, p, q)
+        r0, r1, c0, c1 = bnd
+        info = o.local_solve(before, f, bnd)
+        c_gpu = after[r0, c0] - before[r0, c0]
+        if fp64:
+            dc = abs(c_gpu - info.c)
+            ok = dc <= 1e-10
+        else:
+            expect = (before[r0:r1, c0:c1] + info.c).astype(np.float32).astype(np.float64)
+            dc = float(np.max(np.abs(after[r0:r1, c0:c1] - expect)))
+            ok = dc == 0.0
+        # every pixel of the block moved by the same c
+        assert np.allclose(after[r0:r1, c0:c1] - before[r0:r1, c0:c1], c_gpu, rtol=0, atol=1e-6 if not fp64 else 1e-13)
+        if not ok:
+            v0 = info.K0 + 0.5 * o.p.alpha * info.s * info.fs ** 2
+            d_gpu = o.local_delta(before, f, bnd, c_gpu)
+            d_orc = o.local_delta(before, f, bnd, info.c)
+            assert d_gpu <= d_orc + 1e-12 * (1 + v0) + (0 if fp64 else 1e-7 * (1 + v0)), \
+                (level, colour, p, q, c_gpu, info.c, d_gpu, d_orc)
+            n_equal += 1
+        worst = max(worst, dc)
+    return worst, n_equal
+
+
+def _trajectory(mg, orc, h, w, kind, colours, dtype, cycles, seed, sigma, levels=0):
+    """Run the GPU sweep by sweep for `cycles` V-cycles, checking every sweep against the oracle
+    from the GPU's own state; then compare with the free-running oracle."""
+    fp64 = dtype == torch.float64
+    f, _ = _f_and_u(h, w, seed, sigma, dtype)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, levels=levels, dtype=dtype, fine_colours=colours)
+    o = orc.Oracle(h, w, 20.0, kind, levels=s.levels, fine_colours=colours, round_f32=not fp64, threads=THREADS)
+    fd = dev(f, dtype)
+    ug = dev(f, dtype)
+    uv = dev(f, dtype)   # same run through mg_curv_vcycle
+    worst, n_equal, n_blocks = 0.0, 0, 0
+    for cyc in range(cycles):
+        for level in range(1, s.levels + 1):
+            for colour in range(o.num_colours(level)):
+                before = host(ug)
+                s.sweep(ug, fd, level, colour)
+                after = host(ug)
+                wv, ne = _check_sweep_against_oracle(o, f, before, after, level, colour, fp64)
+                worst = max(worst, wv)
+                n_equal += ne
+                n_blocks += len(_blocks_of(o, level, colour))
+        s.vcycle(uv, fd)
+        assert torch.equal(uv, ug), "mg_curv_vcycle and the sweep sequence must agree bitwise"
+    uo = f.copy()
+    n, trace = o.solve(uo, f, rel_tol=0.0, max_vcycles=cycles)
+    e_gpu = s.energy(ug, fd)
+    du = float(np.max(np.abs(host(ug) - uo)))
+    print(f"sweep parity: max|dc| = {worst:.3e}, equal-minimum blocks {n_equal}/{n_blocks}; "
+          f"free-running max|u_gpu - u_oracle| = {du:.3e}, energy {e_gpu:.10f} vs {trace[-1]:.10f}")
+    assert n_equal <= max(2, n_blocks // 1000)
+    return e_gpu, trace[-1], du
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_config_64_mean_fp64_20_vcycles(mg, orc, seed):
+    """64x64, sigma 0.05, mean curvature, alpha 20, 6 levels, 4 colours, 20 V-cycles, FP64 state:
+    every colour sweep of the GPU trajectory matches the oracle from the same state; the free-running
+    energies agree to the amplification level the oracle itself shows under a 1e-15 perturbation."""
+    _case(f"64x64 MC fp64 seed={seed}")
+    e_gpu, e_orc, du = _trajectory(mg, orc, 64, 64, 0, 4, torch.float64, 20, seed, 0.05, levels=6)
+    assert abs(e_gpu - e_orc) <= 1e-6 * e_orc
+
+
+@pytest.mark.parametrize("kind,colours", [(1, 4), (0, 9), (1, 9)])
+def test_config_64_variants_fp64(mg, orc, kind, colours):
+    _case(f"64x64 kind={kind} colours={colours} fp64")
+    e_gpu, e_orc, du = _trajectory(mg, orc, 64, 64, kind, colours, torch.float64, 20, 0, 0.05, levels=6)
+    assert abs(e_gpu - e_orc) <= 1e-6 * e_orc
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_fp32_state_parity(mg, orc, kind):
+    """FP32 state, FP64 local math: every sweep matches the float-state oracle from the same state, and
+    the free-running run matches it too; against the pure FP64 oracle the energy gap and max |du| are
+    reported (FP32 rounding of the state changes later kink decisions, as any 1e-15 perturbation does)."""
+    h, w = 96, 80
+    _case(f"fp32 state {h}x{w} kind={kind}")
+    e_gpu, e_orc, du = _trajectory(mg, orc, h, w, kind, 4, torch.float32, 15, 4, 0.1)
+    assert du <= 1e-6
+    f, _ = _f_and_u(h, w, 4, 0.1, torch.float32)
+    o64 = orc.Oracle(h, w, 20.0, kind, threads=THREADS)
+    u64 = f.copy()
+    n, t64 = o64.solve(u64, f, rel_tol=0.0, max_vcycles=15)
+    gap = abs(e_gpu - t64[-1]) / t64[-1]
+    print(f"FP32-state GPU vs FP64 oracle: energy gap {gap:.3e}")
+    assert gap <= 1e-4
+
+
+def test_solve_stop_rule_matches_oracle(mg, orc):
+    """Relative energy-change stop: same number of V-cycles and final energy as the oracle."""
+    h, w = 80, 72
+    _case("solve stop rule fp32")
+    f, _ = _f_and_u(h, w, 9, 0.08, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=0, dtype=torch.float32)
+    ug = dev(f, torch.float32)
+    res = s.solve(ug, dev(f, torch.float32), rel_tol=1e-6, max_vcycles=300)
+    o = orc.Oracle(h, w, 20.0, 0, round_f32=True, threads=THREADS)
+    uo = f.copy()
+    n, trace = o.solve(uo, f, rel_tol=1e-6, max_vcycles=300)
+    print(f"gpu vcycles={res['vcycles']} oracle={n}")
+    assert res["status"] == 0
+    assert res["vcycles"] == n
+    assert abs(res["energy"] - trace[-1]) <= 1e-9 * trace[-1]
+    assert np.max(np.abs(host(ug) - uo)) <= 1e-6
+
+
+def test_not_converged_status(mg):
+    f, _ = _f_and_u(32, 32, 1, 0.1, torch.float32)
+    s = mg.Solver(32, 32, dtype=torch.float32)
+    res = s.solve(dev(f, torch.float32), dev(f, torch.float32).clone(), rel_tol=1e-14, max_vcycles=2)
+    assert res["status"] == mg.MG_NOT_CONVERGED and res["vcycles"] == 2
+
+
+def _sampled_check(mg, orc, h, w, kind, dtype, levels_to_check, n_samples, warm_cycles, seed=0, sigma=0.1):
+    f, _ = _f_and_u(h, w, seed, sigma, dtype)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=(dtype == torch.float32))
+    fd = dev(f, dtype)
+    ug = dev(f, dtype)
+    for _ in range(warm_cycles):
+        s.vcycle(ug, fd)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for level in levels_to_check:
+        colour = int(rng.integers(0, 4))
+        _case(f"sampled {h}x{w} kind={kind} {dtype} level={level} colour={colour}")
+        before = host(ug)
+        s.sweep(ug, fd, level, colour)
+        after = host(ug)
+        m, n = o.grid(level)
+        cand = [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
+        pick = rng.choice(len(cand), size=min(n_samples, len(cand)), replace=False)
+        for k in pick:
+            p, q = cand[int(k)]
+            r0, r1, c0, c1 = o.block_bounds(level, p, q)
+            info = o.local_solve(before, f, (r0, r1, c0, c1))
+            expect = before[r0:r1, c0:c1] + info.c
+            if dtype == torch.float32:
+                expect = expect.astype(np.float32).astype(np.float64)
+            err = np.max(np.abs(after[r0:r1, c0:c1] - expect))
+            worst = max(worst, err)
+            tol = 1e-12 if dtype == torch.float64 else 2.5e-7
+            assert err <= tol, (level, p, q, err, info.c)
+    return worst
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_sampled_parity_1024_fp32(mg, orc, kind):
+    """1024x1024 in the launch configuration the benchmark times: sampled blocks of one colour
+    at fine, middle and coarsest levels against the oracle's local solve on the same state."""
+    worst = _sampled_check(mg, orc, 1024, 1024, kind, torch.float32, [1, 2, 3, 5, 8, 10], 24, 3)
+    print(f"worst sampled error {worst:.3e}")
+
+
+def test_sampled_parity_1024_fp64(mg, orc):
+    worst = _sampled_check(mg, orc, 1024, 1024, 0, torch.float64, [1, 2, 4, 6, 9, 10], 16, 2)
+    print(f"worst sampled error {worst:.3e}")
+
+
+def test_sampled_parity_streamed_coarse_blocks(mg, orc):
+    """Blocks of side >= 1024 stream their ring from memory at every evaluation."""
+    worst = _sampled_check(mg, orc, 1536, 1200, 0, torch.float32, [11, 9], 4, 1)
+    print(f"worst sampled error {worst:.3e}")
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (2, 3), (3, 2), (5, 7), (33, 65), (65, 33)])
+def test_small_and_ragged_shapes_fp64(mg, orc, shape):
+    h, w = shape
+    _case(f"ragged {shape}")
+    _trajectory(mg, orc, h, w, 0, 4, torch.float64, 4, 6, 0.1)
+
+
+def test_deterministic_bitwise(mg):
+    _case("determinism 256x256")
+    f, _ = _f_and_u(256, 256, 2, 0.1, torch.float32)
+    s = mg.Solver(256, 256, dtype=torch.float32)
+    fd = dev(f, torch.float32)
+    outs = []
+    for _ in range(2):
+        ug = dev(f, torch.float32)
+        for _ in range(3):
+            s.vcycle(ug, fd)
+        outs.append(host(ug))
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_constant_image_is_fixed_point(mg, dtype):
+    f = np.full((40, 56), 0.375)
+    s = mg.Solver(40, 56, dtype=dtype)
+    ug = dev(f, dtype)
+    s.solve(ug, dev(f, dtype), rel_tol=0.0, max_vcycles=3)
+    assert np.array_equal(host(ug), f)
+
+
+def test_error_paths(mg):
+    f, _ = _f_and_u(32, 32, 1, 0.1, torch.float32)
+    s = mg.Solver(32, 32, dtype=torch.float32)
+    fd = dev(f, torch.float32)
+    with pytest.raises(mg.MgCurvError) as ei:
+        s.vcycle(fd, fd)
+    assert ei.value.status == -1
+    bad = f.copy()
+    bad[3, 4] = np.nan
+    ub = dev(f, torch.float32)
+    before = host(ub)
+    with pytest.raises(mg.MgCurvError) as ei:
+        s.solve(ub, dev(bad, torch.float32), rel_tol=1e-6, max_vcycles=3)
+    assert ei.value.status == -6
+    assert np.array_equal(host(ub), before)
+    with pytest.raises(ValueError):
+        s.vcycle(dev(f[:16], torch.float32), fd)
+    with pytest.raises(TypeError):
+        s.vcycle(dev(f, torch.float64), fd)
