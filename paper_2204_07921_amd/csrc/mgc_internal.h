@@ -14,10 +14,23 @@ struct LaunchCtx {
     int M, G;   // samples, bisection steps
 };
 
+// Scratch of the coarse (lazily applied) levels.
+struct CoarseScratch {
+    double* partials;  // per block and row chunk: partial sums of f - u
+    int nchunk;        // set by launch_level_begin
+    double* cpend;     // pending corrections, m_j x n_j
+};
+
 // b = 1: colour sweep from uin into uout (every pixel of uout is written).
 hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours);
-// b >= 2: colour sweep in place.
-hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour);
+// b >= 2: colour sweep (in place on fine levels, into cs.cpend on coarse levels).
+hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, const CoarseScratch& cs);
+// Coarse levels (level_is_lazy(b)): block sums and zeroed corrections before the
+// colours, the correction pass after them.
+bool level_is_lazy(int b);
+void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_per);
+hipError_t launch_level_begin(const LaunchCtx& L, const void* u, const void* f, int b, CoarseScratch& cs);
+hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScratch& cs);
 // F(u) into out[0] (device), using partials (energy_partials_count doubles).
 hipError_t launch_energy(const LaunchCtx& L, const void* u, const void* f, double* partials, double* out);
 int energy_partials_count(int H, int W);

@@ -41,19 +41,22 @@ __global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__
             for (int dx = -1; dx <= 1; ++dx)
                 make_ring(uin, H, W, i + dy, j + dx, i, i + 1, j, j + 1, rg[(dy + 1) * 3 + dx + 1]);
         const double fs = (double)f[(size_t)i * W + j] - (double)uin[(size_t)i * W + j];
-        auto K = [&](double c) {
-            double acc = 0.0;
+        auto Kpart = [&](const auto& cs, auto& out) {
+            constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
-            for (int t = 0; t < 9; ++t) acc += abs_kappa<KIND>(rg[t], c);
-            return acc;
+            for (int k = 0; k < N; ++k) out[k] = 0.0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int k = 0; k < N; ++k) out[k] += abs_kappa<KIND>(rg[t], cs[k]);
         };
-        auto D = [&](double c) {
+        auto Dpart = [&](double c) {
             double acc = 0.0;
 #pragma unroll
             for (int t = 0; t < 9; ++t) acc += dabs_kappa<KIND>(rg[t], c);
             return acc;
         };
-        cval = local_solve(K, D, fs, alpha, M, G);
+        cval = local_solve(Kpart, Dpart, NoSum(), fs, alpha, M, G);
     }
     // write the cell
 #pragma unroll
@@ -101,22 +104,41 @@ __device__ __forceinline__ void band_pixel(int k, int r0, int r1, int c0, int c1
 }
 
 // ---------------------------------------------------------------------------
-// Block levels (b >= 2), in place.  GROUP lanes per block; each lane keeps RPL
-// ring records in registers (RPL = 0: records are rebuilt from memory at every
+// Block levels (b >= 2).  GROUP lanes per block; each lane keeps RPL ring
+// records in registers (RPL = 0: records are rebuilt from memory at every
 // evaluation, for blocks whose ring does not fit in registers).
+//
+// Fine block levels (LAZY = false) sum f - u over the block themselves and add
+// c to the block in place.  Coarse levels (LAZY = true) read the block's sum
+// from partial sums taken once at the start of the level (the other colours of
+// a level never touch this block's pixels), see the corrections of the
+// level's earlier colours through the pending array `cpend`, and store their
+// own c there; one wide pass applies the level at its end.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND, int GROUP, int RPL, class GSum>
+struct CoarseArgs {
+    const double* partials;  // per block: nchunk partial sums of f - u
+    int nchunk;
+    double* cpend;           // m_j x n_j pending corrections of this level
+    int nj;
+    int lb;                  // log2(b)
+};
+
+template <typename T, int KIND, int GROUP, int RPL, bool LAZY, class GSum>
 __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restrict__ f, int H, int W,
-                                            int r0, int r1, int c0, int c1, int lane, double alpha, int M, int G,
-                                            const GSum& gsum)
+                                            int p, int q, int r0, int r1, int c0, int c1, int lane,
+                                            double alpha, int M, int G, const GSum& gsum, const CoarseArgs& ca)
 {
     const int h = r1 - r0, w = c1 - c0;
-    // r = sum over B of (f - u)
     double r = 0.0;
-    for (int k = lane; k < h * w; k += GROUP) {
-        const int i = r0 + k / w, j = c0 + k % w;
-        const size_t idx = (size_t)i * W + j;
-        r += (double)f[idx] - (double)u[idx];
+    if (LAZY) {
+        const double* part = ca.partials + ((size_t)p * ca.nj + q) * ca.nchunk;
+        for (int k = lane; k < ca.nchunk; k += GROUP) r += part[k];
+    } else {
+        for (int k = lane; k < h * w; k += GROUP) {
+            const int i = r0 + k / w, j = c0 + k % w;
+            const size_t idx = (size_t)i * W + j;
+            r += (double)f[idx] - (double)u[idx];
+        }
     }
     r = gsum(r);
     const double s = (double)h * (double)w;
@@ -132,50 +154,57 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             if (k < ncand) {
                 int i, j;
                 band_pixel(k, r0, r1, c0, c1, i, j);
-                make_ring(u, H, W, i, j, r0, r1, c0, c1, rg[t]);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rg[t], ca.cpend, ca.nj, ca.lb);
             } else {
                 zero_ring(rg[t]);
             }
         }
-        auto K = [&](double c) {
-            double acc = 0.0;
+        auto Kpart = [&](const auto& cs, auto& out) {
+            constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
-            for (int t = 0; t < RPL; ++t) acc += abs_kappa<KIND>(rg[t], c);
-            return gsum(acc);
+            for (int k = 0; k < N; ++k) out[k] = 0.0;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t)
+#pragma unroll
+                for (int k = 0; k < N; ++k) out[k] += abs_kappa<KIND>(rg[t], cs[k]);
         };
-        auto D = [&](double c) {
+        auto Dpart = [&](double c) {
             double acc = 0.0;
 #pragma unroll
             for (int t = 0; t < RPL; ++t) acc += dabs_kappa<KIND>(rg[t], c);
-            return gsum(acc);
+            return acc;
         };
-        cval = local_solve(K, D, fs, alpha * s, M, G);
+        cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);
     } else {
-        auto K = [&](double c) {
-            double acc = 0.0;
-            for (int k = lane; k < ncand; k += GROUP) {
+        auto Kpart = [&](const auto& cs, auto& out) {
+            constexpr int N = sizeof(out) / sizeof(double);
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k] = 0.0;
+            for (int kk = lane; kk < ncand; kk += GROUP) {
                 int i, j;
                 Ring rr;
-                band_pixel(k, r0, r1, c0, c1, i, j);
-                make_ring(u, H, W, i, j, r0, r1, c0, c1, rr);
-                acc += abs_kappa<KIND>(rr, c);
+                band_pixel(kk, r0, r1, c0, c1, i, j);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
+#pragma unroll
+                for (int k = 0; k < N; ++k) out[k] += abs_kappa<KIND>(rr, cs[k]);
             }
-            return gsum(acc);
         };
-        auto D = [&](double c) {
+        auto Dpart = [&](double c) {
             double acc = 0.0;
-            for (int k = lane; k < ncand; k += GROUP) {
+            for (int kk = lane; kk < ncand; kk += GROUP) {
                 int i, j;
                 Ring rr;
-                band_pixel(k, r0, r1, c0, c1, i, j);
-                make_ring(u, H, W, i, j, r0, r1, c0, c1, rr);
+                band_pixel(kk, r0, r1, c0, c1, i, j);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
                 acc += dabs_kappa<KIND>(rr, c);
             }
-            return gsum(acc);
+            return acc;
         };
-        cval = local_solve(K, D, fs, alpha * s, M, G);
+        cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);
     }
-    if (cval != 0.0) {
+    if (LAZY) {
+        if (lane == 0) ca.cpend[(size_t)p * ca.nj + q] = cval;
+    } else if (cval != 0.0) {
         for (int k = lane; k < h * w; k += GROUP) {
             const int i = r0 + k / w, j = c0 + k % w;
             const size_t idx = (size_t)i * W + j;
@@ -185,27 +214,75 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
 }
 
 // Blocks of colour (pr, pc) at side b: block (p, q) = (2 bi + pr, 2 bj + pc), bi < nbr, bj < nbc.
-template <typename T, int KIND, int GROUP, int RPL>
+template <typename T, int KIND, int GROUP, int RPL, bool LAZY>
 __global__ __launch_bounds__(GROUP >= 256 ? GROUP : 256) void sweep_blocks_kernel(
     T* __restrict__ u, const T* __restrict__ f, int H, int W, int b, int pr, int pc, int nbr, int nbc,
-    double alpha, int M, int G)
+    double alpha, int M, int G, CoarseArgs ca)
 {
     if constexpr (GROUP <= 64) {
         const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / GROUP;
         const int lane = threadIdx.x & (GROUP - 1);
         if (gid >= nbr * nbc) return;  // whole groups exit together
         const int bi = gid / nbc, bj = gid - bi * nbc;
-        const int r0 = (2 * bi + pr) * b, c0 = (2 * bj + pc) * b;
+        const int p = 2 * bi + pr, q = 2 * bj + pc;
+        const int r0 = p * b, c0 = q * b;
         const int r1 = min(r0 + b, H), c1 = min(c0 + b, W);
-        solve_block<T, KIND, GROUP, RPL>(u, f, H, W, r0, r1, c0, c1, lane, alpha, M, G, WaveSum<GROUP>());
+        solve_block<T, KIND, GROUP, RPL, LAZY>(u, f, H, W, p, q, r0, r1, c0, c1, lane, alpha, M, G,
+                                               WaveSum<GROUP>(), ca);
     } else {
-        __shared__ double lds[2 * (GROUP / 64)];
+        __shared__ double lds[2 * (GROUP / 64) * BlockSum<GROUP>::NMAX];
         const int gid = blockIdx.x;
         const int bi = gid / nbc, bj = gid - bi * nbc;
-        const int r0 = (2 * bi + pr) * b, c0 = (2 * bj + pc) * b;
+        const int p = 2 * bi + pr, q = 2 * bj + pc;
+        const int r0 = p * b, c0 = q * b;
         const int r1 = min(r0 + b, H), c1 = min(c0 + b, W);
         BlockSum<GROUP> gs{lds, 0};
-        solve_block<T, KIND, GROUP, RPL>(u, f, H, W, r0, r1, c0, c1, threadIdx.x, alpha, M, G, gs);
+        solve_block<T, KIND, GROUP, RPL, LAZY>(u, f, H, W, p, q, r0, r1, c0, c1, threadIdx.x, alpha, M, G, gs, ca);
+    }
+}
+
+// Coarse levels: partial sums of f - u, one workgroup per (block, chunk of rows).
+// partials[(p * nj + q) * nchunk + k] = sum over rows [r0 + k rows_per, ...) of block (p, q).
+template <typename T>
+__global__ __launch_bounds__(256) void block_sums_kernel(const T* __restrict__ u, const T* __restrict__ f, int H,
+                                                         int W, int b, int nj, int nchunk, int rows_per,
+                                                         double* __restrict__ partials)
+{
+    __shared__ double lds[4];
+    const int blk = blockIdx.x / nchunk, k = blockIdx.x - blk * nchunk;
+    const int p = blk / nj, q = blk - p * nj;
+    const int c0 = q * b, c1 = min(c0 + b, W), w = c1 - c0;
+    const int ra = p * b + k * rows_per;
+    const int rb = min(min(ra + rows_per, (p + 1) * b), H);
+    double acc = 0.0;
+    const int n = (rb > ra ? rb - ra : 0) * w;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = ra + t / w, j = c0 + t % w;
+        const size_t idx = (size_t)i * W + j;
+        acc += (double)f[idx] - (double)u[idx];
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double* __restrict__ x, size_t n, double v)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) x[t] = v;
+}
+
+// End of a coarse level: u <- u + c of the pixel's block (rounded to the state type).
+template <typename T>
+__global__ __launch_bounds__(256) void apply_level_kernel(T* __restrict__ u, int H, int W, int lb, int nj,
+                                                          const double* __restrict__ cpend)
+{
+    const size_t n = (size_t)H * W;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t / W), j = (int)(t - (size_t)i * W);
+        const double c = cpend[(size_t)(i >> lb) * nj + (j >> lb)];
+        if (c != 0.0) u[t] = (T)((double)u[t] + c);
     }
 }
 
@@ -273,8 +350,9 @@ hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, 
                   : launch_pixels_t<float, 0>(L, uin, uout, f, colour, nc);
 }
 
-template <typename T, int KIND, int GROUP, int RPL>
-static hipError_t launch_blocks_cfg(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr, int nbc)
+template <typename T, int KIND, int GROUP, int RPL, bool LAZY>
+static hipError_t launch_blocks_cfg(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr,
+                                    int nbc, const CoarseArgs& ca)
 {
     const int groups = nbr * nbc;
     if (groups == 0) return hipSuccess;
@@ -286,38 +364,91 @@ static hipError_t launch_blocks_cfg(const LaunchCtx& L, void* u, const void* f, 
         block = dim3(GROUP);
         grid = dim3(groups);
     }
-    hipLaunchKernelGGL((sweep_blocks_kernel<T, KIND, GROUP, RPL>), grid, block, 0, L.stream, (T*)u, (const T*)f,
-                       L.H, L.W, b, pr, pc, nbr, nbc, L.alpha, L.M, L.G);
+    hipLaunchKernelGGL((sweep_blocks_kernel<T, KIND, GROUP, RPL, LAZY>), grid, block, 0, L.stream, (T*)u,
+                       (const T*)f, L.H, L.W, b, pr, pc, nbr, nbc, L.alpha, L.M, L.G, ca);
     return hipGetLastError();
 }
 
 template <typename T, int KIND>
-static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr, int nbc)
+static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr,
+                                  int nbc, const CoarseArgs& ca)
 {
     // ring size of an unclipped block is 8b
     switch (b) {
-    case 2: return launch_blocks_cfg<T, KIND, 16, 1>(L, u, f, b, pr, pc, nbr, nbc);
-    case 4: return launch_blocks_cfg<T, KIND, 32, 1>(L, u, f, b, pr, pc, nbr, nbc);
-    case 8: return launch_blocks_cfg<T, KIND, 64, 1>(L, u, f, b, pr, pc, nbr, nbc);
-    case 16: return launch_blocks_cfg<T, KIND, 64, 2>(L, u, f, b, pr, pc, nbr, nbc);
-    case 32: return launch_blocks_cfg<T, KIND, 64, 4>(L, u, f, b, pr, pc, nbr, nbc);
-    case 64: return launch_blocks_cfg<T, KIND, 256, 2>(L, u, f, b, pr, pc, nbr, nbc);
-    case 128: return launch_blocks_cfg<T, KIND, 256, 4>(L, u, f, b, pr, pc, nbr, nbc);
-    case 256: return launch_blocks_cfg<T, KIND, 1024, 2>(L, u, f, b, pr, pc, nbr, nbc);
-    case 512: return launch_blocks_cfg<T, KIND, 1024, 4>(L, u, f, b, pr, pc, nbr, nbc);
-    default: return launch_blocks_cfg<T, KIND, 1024, 0>(L, u, f, b, pr, pc, nbr, nbc);
+    case 2: return launch_blocks_cfg<T, KIND, 16, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 4: return launch_blocks_cfg<T, KIND, 32, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 8: return launch_blocks_cfg<T, KIND, 64, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 16: return launch_blocks_cfg<T, KIND, 64, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 32: return launch_blocks_cfg<T, KIND, 64, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 64: return launch_blocks_cfg<T, KIND, 256, 2, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 128: return launch_blocks_cfg<T, KIND, 256, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 256: return launch_blocks_cfg<T, KIND, 512, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 512: return launch_blocks_cfg<T, KIND, 512, 8, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    default: return launch_blocks_cfg<T, KIND, 1024, 0, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     }
 }
 
-hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour)
+bool level_is_lazy(int b) { return b >= 64; }
+
+hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, const CoarseScratch& cs)
 {
     const int pr = colour >> 1, pc = colour & 1;
     const int mj = (L.H + b - 1) / b, nj = (L.W + b - 1) / b;
     const int nbr = (mj - pr + 1) / 2, nbc = (nj - pc + 1) / 2;
-    if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc)
-                             : launch_blocks_t<double, 0>(L, u, f, b, pr, pc, nbr, nbc);
-    return L.kind ? launch_blocks_t<float, 1>(L, u, f, b, pr, pc, nbr, nbc)
-                  : launch_blocks_t<float, 0>(L, u, f, b, pr, pc, nbr, nbc);
+    CoarseArgs ca{cs.partials, cs.nchunk, cs.cpend, nj, 0};
+    while ((1 << ca.lb) < b) ++ca.lb;
+    if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)
+                             : launch_blocks_t<double, 0>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    return L.kind ? launch_blocks_t<float, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)
+                  : launch_blocks_t<float, 0>(L, u, f, b, pr, pc, nbr, nbc, ca);
+}
+
+void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_per)
+{
+    const int mj = (H + b - 1) / b, nj = (W + b - 1) / b;
+    int rp = 16384 / b;              // about 16k pixels per chunk
+    if (rp < 1) rp = 1;
+    if (rp > b) rp = b;
+    *rows_per = rp;
+    *nchunk = (b + rp - 1) / rp;
+    *nblocks = mj * nj;
+}
+
+hipError_t launch_level_begin(const LaunchCtx& L, const void* u, const void* f, int b, CoarseScratch& cs)
+{
+    int nblocks, nchunk, rows_per;
+    coarse_geometry(L.H, L.W, b, &nblocks, &nchunk, &rows_per);
+    cs.nchunk = nchunk;
+    const int nj = (L.W + b - 1) / b;
+    dim3 grid((unsigned)nblocks * nchunk), block(256);
+    if (L.f64)
+        hipLaunchKernelGGL(block_sums_kernel<double>, grid, block, 0, L.stream, (const double*)u, (const double*)f,
+                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials);
+    else
+        hipLaunchKernelGGL(block_sums_kernel<float>, grid, block, 0, L.stream, (const float*)u, (const float*)f,
+                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t n = (size_t)nblocks;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, cs.cpend, n, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScratch& cs)
+{
+    const int nj = (L.W + b - 1) / b;
+    int lb = 0;
+    while ((1 << lb) < b) ++lb;
+    const size_t n = (size_t)L.H * L.W;
+    size_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (L.f64)
+        hipLaunchKernelGGL(apply_level_kernel<double>, dim3((unsigned)g), dim3(256), 0, L.stream, (double*)u, L.H, L.W,
+                           lb, nj, (const double*)cs.cpend);
+    else
+        hipLaunchKernelGGL(apply_level_kernel<float>, dim3((unsigned)g), dim3(256), 0, L.stream, (float*)u, L.H, L.W,
+                           lb, nj, (const double*)cs.cpend);
+    return hipGetLastError();
 }
 
 int energy_partials_count(int H, int W)

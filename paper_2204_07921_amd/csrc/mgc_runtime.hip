@@ -20,6 +20,7 @@ struct mg_curv_ctx {
     hipStream_t stream;
     void* pingpong;        // H x W state-dtype image for the two-phase pixel level
     double* partials;      // energy partial sums
+    mgc::CoarseScratch coarse;  // block sums and pending corrections of the coarse levels
     double* energy_dev;    // one double
     double* energy_host;   // pinned host double
     std::string err;
@@ -96,14 +97,19 @@ mg_status sweep(mg_curv_ctx* ctx, void* u, const void* f, int level, int colour)
         if (e != hipSuccess) return hip_fail(ctx, e, "pixel sweep copy");
         return MG_OK;
     }
-    e = mgc::launch_sweep_blocks(L, u, f, 1 << (level - 1), colour);
+    const int b = 1 << (level - 1);
+    const bool lazy = mgc::level_is_lazy(b);
+    if (lazy && (e = mgc::launch_level_begin(L, u, f, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level begin");
+    e = mgc::launch_sweep_blocks(L, u, f, b, colour, ctx->coarse);
     if (e != hipSuccess) return hip_fail(ctx, e, "block sweep launch");
+    if (lazy && (e = mgc::launch_level_end(L, u, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level end");
     return MG_OK;
 }
 
 // All colours of one level.  The pixel level ping-pongs between u and the
 // scratch image (two-phase update); with an odd number of colours the result
-// is copied back into u.
+// is copied back into u.  Coarse levels take their block sums first and apply
+// the level's corrections after the last colour.
 mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level)
 {
     const mgc::LaunchCtx L = launch_ctx(ctx);
@@ -123,10 +129,14 @@ mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level)
         }
         return MG_OK;
     }
+    const int b = 1 << (level - 1);
+    const bool lazy = mgc::level_is_lazy(b);
+    if (lazy && (e = mgc::launch_level_begin(L, u, f, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level begin");
     for (int colour = 0; colour < 4; ++colour) {
-        e = mgc::launch_sweep_blocks(L, u, f, 1 << (level - 1), colour);
+        e = mgc::launch_sweep_blocks(L, u, f, b, colour, ctx->coarse);
         if (e != hipSuccess) return hip_fail(ctx, e, "block sweep launch");
     }
+    if (lazy && (e = mgc::launch_level_end(L, u, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level end");
     return MG_OK;
 }
 
@@ -201,10 +211,22 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->partials = nullptr;
     c->energy_dev = nullptr;
     c->energy_host = nullptr;
+    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
     const int np = mgc::energy_partials_count(p.height, p.width);
+    size_t n_part = 1, n_pend = 1;
+    for (int level = 2; level <= c->J; ++level) {
+        const int b = 1 << (level - 1);
+        if (!mgc::level_is_lazy(b)) continue;
+        int nblocks, nchunk, rows_per;
+        mgc::coarse_geometry(p.height, p.width, b, &nblocks, &nchunk, &rows_per);
+        if ((size_t)nblocks * nchunk > n_part) n_part = (size_t)nblocks * nchunk;
+        if ((size_t)nblocks > n_pend) n_pend = (size_t)nblocks;
+    }
     if (hipMalloc(&c->pingpong, nb) != hipSuccess || hipMalloc((void**)&c->partials, sizeof(double) * np) != hipSuccess ||
+        hipMalloc((void**)&c->coarse.partials, sizeof(double) * n_part) != hipSuccess ||
+        hipMalloc((void**)&c->coarse.cpend, sizeof(double) * n_pend) != hipSuccess ||
         hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         mg_curv_destroy(c);
@@ -288,6 +310,8 @@ void mg_curv_destroy(mg_curv_ctx* ctx)
     if (ctx->stream || ctx->pingpong) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->pingpong) (void)hipFree(ctx->pingpong);
     if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->coarse.partials) (void)hipFree(ctx->coarse.partials);
+    if (ctx->coarse.cpend) (void)hipFree(ctx->coarse.cpend);
     if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
     if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
     delete ctx;

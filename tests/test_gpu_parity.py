@@ -88,6 +88,33 @@ def test_single_sweep_parity_every_level(mg, orc, kind, colours, dtype):
             assert n_equal <= 1, (level, colour, n_equal)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_single_sweep_parity_coarse_levels(mg, orc, kind, dtype):
+    """A ragged 300x260 image: the coarse levels (block side 64..256, corrections applied lazily at the
+    end of a level) against the oracle, sweep by sweep, plus one whole level through mg_curv_level."""
+    h, w = 300, 260
+    f, u0 = _f_and_u(h, w, 8, 0.1, dtype, perturb=0.05)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=(dtype == torch.float32), threads=THREADS)
+    fd = dev(f, dtype)
+    for level in range(2, o.levels + 1):
+        ug = dev(u0, dtype)
+        before = u0.copy()
+        for colour in range(4):
+            _case(f"coarse sweep {h}x{w} kind={kind} {dtype} level={level} colour={colour}")
+            s.sweep(ug, fd, level, colour)
+            after = host(ug)
+            worst, n_equal = _check_sweep_against_oracle(o, f, before, after, level, colour,
+                                                         fp64=dtype == torch.float64)
+            assert n_equal <= 1, (level, colour, n_equal)
+            before = after
+        # the same four colours through one mg_curv_level call (pending corrections)
+        ul = dev(u0, dtype)
+        s.level(ul, fd, level)
+        assert torch.equal(ul, ug), level
+
+
 def _blocks_of(o, level, colour):
     m, n = o.grid(level)
     return [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
