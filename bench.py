@@ -11,8 +11,8 @@ the script also runs full solves from u = f to a relative energy change below
 
 The roofline entry is for the dominant kernel (the pixel-level sweep): its
 average launch time comes from HIP events around the pixel level on the
-library's stream; its work is counted in algorithmic FP64 operations (see
-the design doc for the per-evaluation count).  The CPU baseline times the FP64 C
+library's stream; its work is counted in algorithmic FP64 operations per
+ring-pixel evaluation (constants below).  The CPU baseline times the FP64 C
 oracle on this machine's cores over a bounded sample (whole V-cycles at
 1024x1024).
 """
@@ -56,6 +56,33 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_sources_sha() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2204_07921_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str, kernel_prefix: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (already scaled by the copy-kernel calibration), or None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        doc = json.load(fh).get(workload_key)
+    if not doc or doc.get("sources_sha") != kernel_sources_sha():
+        return None
+    for name, k in doc["kernels"].items():
+        if name.startswith(kernel_prefix):
+            return int(round((k["fetch_kib"] + k["write_kib"]) * 1024))
+    return None
+
+
 def cpu_baseline(f64: np.ndarray, kind: int, vcycles: int) -> dict:
     import oracle
     threads = min(os.cpu_count() or 1, 16)
@@ -73,8 +100,8 @@ def cpu_baseline(f64: np.ndarray, kind: int, vcycles: int) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is described "
-                          "in DESIGN.md and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the path has no multi-GPU "
+                          "sharding)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2204_07921_amd import mgcurv
@@ -162,7 +189,10 @@ def main():
                    "image": [H, W], "levels": J, "alpha": ALPHA, "sigma": SIGMA,
                    "state_dtype": "f32", "local_math": "f64", "samples": 16, "bisections": 32},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic(f"1024x1024_{'mean' if args.kind == 0 else 'gauss'}_f32",
+                                                 f"mgc::sweep_pixels_kernel<float, {args.kind}"),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "sweep_pixels_kernel (b = 1)", "avg_launch_ms": round(avg_ms, 5),
                      "flops_per_launch": flops_launch},
         "level_ms": level_ms,
