@@ -128,6 +128,70 @@ void mg_curv_destroy(mg_curv_ctx *ctx);
  * failed mg_curv_init when ctx is NULL.  Never NULL. */
 const char *mg_curv_last_error(const mg_curv_ctx *ctx);
 
+
+/* ------------------------------------------------------------------------
+ * Batched images.  n images of independent sizes, alphas and curvature kinds
+ * share one packed float32 buffer for u and one for f: image i occupies
+ * elements [mg_curv_batch_offset(b, i), mg_curv_batch_offset(b, i + 1)) in
+ * row-major H_i x W_i order.  Each image follows exactly the single-image
+ * algorithm above with its own level count J_i; one V-cycle runs levels
+ * 1 .. max J_i, and each (level, colour) is one persistent kernel over the
+ * work items of all images (images with J_i < level have none).
+ * Requirements: state_dtype MG_F32 and fine_colours 4 for every image;
+ * samples and bisections equal across the batch.  The batch owns a packed
+ * ping-pong buffer and small per-level tables; it is bound to one device and
+ * stream and is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct mg_curv_batch mg_curv_batch;
+
+/* Validate params[0 .. n-1] and allocate the batch.  Errors as mg_curv_init. */
+mg_status mg_curv_batch_init(const mg_curv_params *params, int32_t n, void *hip_stream, mg_curv_batch **out);
+
+/* Element offset of image i in the packed buffers; i = n gives the total
+ * element count.  -1 for a bad argument. */
+int64_t mg_curv_batch_offset(const mg_curv_batch *b, int32_t i);
+
+/* Largest level count J_i of the batch. */
+int32_t mg_curv_batch_levels(const mg_curv_batch *b);
+
+/* One V-cycle for every image (enqueued on the batch's stream).  If
+ * energies is non-null (host array of n doubles) it receives each image's
+ * F(u) afterwards and the call waits. */
+mg_status mg_curv_batch_vcycle(mg_curv_batch *b, void *u, const void *f, double *energies);
+
+/* All colours of one level (1-based) for every image; enqueued only. */
+mg_status mg_curv_batch_level(mg_curv_batch *b, void *u, const void *f, int32_t level);
+
+/* One colour of one block level (level >= 2) for every image; enqueued only. */
+mg_status mg_curv_batch_sweep(mg_curv_batch *b, void *u, const void *f, int32_t level, int32_t colour);
+
+/* Per-image F(u) (host array of n doubles, FP64, fixed summation order). */
+mg_status mg_curv_batch_energy(mg_curv_batch *b, const void *u, const void *f, double *energies);
+
+/* Solve every image until its own relative energy change is below rel_tol
+ * (or max_vcycles).  Converged images stop being updated while the others
+ * continue.  One V-cycle plus the energies is captured once as a HIP graph
+ * on the batch's internal stream and replayed.  Outputs are host arrays of n
+ * entries (each nullable).  Returns MG_OK when every image converged,
+ * MG_NOT_CONVERGED otherwise (status[i] tells which), or an error. */
+mg_status mg_curv_batch_solve(mg_curv_batch *b, void *u, const void *f, double rel_tol, int32_t max_vcycles,
+                              int32_t *vcycles_done, double *final_energy, int32_t *status);
+
+/* Autotune: for each level, time the compiled lane-group shapes and
+ * persistent grid sizes on these buffers (u is not modified; a scratch copy
+ * is used) and keep the fastest.  `repeats` timings per candidate.
+ * Different shapes change only the order of floating-point sums. */
+mg_status mg_curv_batch_tune(mg_curv_batch *b, void *u, const void *f, int32_t repeats);
+
+/* Inspect / force the lane-group shape (group lanes, ring records per lane)
+ * and persistent grid of one level.  set_config rejects shapes that are not
+ * compiled for that level. */
+int32_t mg_curv_batch_config(const mg_curv_batch *b, int32_t level, int32_t *group, int32_t *records, int32_t *grid);
+mg_status mg_curv_batch_set_config(mg_curv_batch *b, int32_t level, int32_t group, int32_t records, int32_t grid);
+
+void mg_curv_batch_destroy(mg_curv_batch *b);
+const char *mg_curv_batch_last_error(const mg_curv_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

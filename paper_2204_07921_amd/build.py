@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgcurv.so")
 
-SOURCES = ["mgc_kernels.hip", "mgc_runtime.hip"]
-HEADERS = ["mgc_device.h", "mgc_internal.h"]
+SOURCES = ["mgc_kernels.hip", "mgc_runtime.hip", "mgc_batch.hip"]
+HEADERS = ["mgc_device.h", "mgc_internal.h", "mgc_sweep.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -36,17 +36,23 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libmgcurv.so; always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
     objs = []
+    cmds = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for rc in ex.map(subprocess.call, cmds):
+            if rc != 0:
+                raise subprocess.CalledProcessError(rc, "hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -56,6 +56,34 @@ def _load() -> C.CDLL:
     L.mg_curv_sweep.argtypes = [vp, vp, cvp, C.c_int32, C.c_int32]
     L.mg_curv_level.restype = C.c_int
     L.mg_curv_level.argtypes = [vp, vp, cvp, C.c_int32]
+    L.mg_curv_batch_init.restype = C.c_int
+    L.mg_curv_batch_init.argtypes = [P, C.c_int32, vp, C.POINTER(vp)]
+    L.mg_curv_batch_offset.restype = C.c_int64
+    L.mg_curv_batch_offset.argtypes = [vp, C.c_int32]
+    L.mg_curv_batch_levels.restype = C.c_int32
+    L.mg_curv_batch_levels.argtypes = [vp]
+    L.mg_curv_batch_vcycle.restype = C.c_int
+    L.mg_curv_batch_vcycle.argtypes = [vp, vp, cvp, C.POINTER(C.c_double)]
+    L.mg_curv_batch_level.restype = C.c_int
+    L.mg_curv_batch_level.argtypes = [vp, vp, cvp, C.c_int32]
+    L.mg_curv_batch_sweep.restype = C.c_int
+    L.mg_curv_batch_sweep.argtypes = [vp, vp, cvp, C.c_int32, C.c_int32]
+    L.mg_curv_batch_energy.restype = C.c_int
+    L.mg_curv_batch_energy.argtypes = [vp, cvp, cvp, C.POINTER(C.c_double)]
+    L.mg_curv_batch_solve.restype = C.c_int
+    L.mg_curv_batch_solve.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+    L.mg_curv_batch_tune.restype = C.c_int
+    L.mg_curv_batch_tune.argtypes = [vp, vp, cvp, C.c_int32]
+    L.mg_curv_batch_config.restype = C.c_int32
+    L.mg_curv_batch_config.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
+    L.mg_curv_batch_set_config.restype = C.c_int
+    L.mg_curv_batch_set_config.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.mg_curv_batch_destroy.restype = None
+    L.mg_curv_batch_destroy.argtypes = [vp]
+    L.mg_curv_batch_last_error.restype = C.c_char_p
+    L.mg_curv_batch_last_error.argtypes = [vp]
     L.mg_curv_levels.restype = C.c_int32
     L.mg_curv_levels.argtypes = [vp]
     L.mg_curv_destroy.restype = None
@@ -195,3 +223,97 @@ class Solver:
 
     def level(self, u, f, level):
         return mg_curv_level(self.ctx, self.params, u, f, level)
+
+
+# --- batched images ----------------------------------------------------------------
+
+def _bcheck(status: int, b=None) -> int:
+    if status < 0:
+        raise MgCurvError(status, lib.mg_curv_batch_last_error(b).decode())
+    return status
+
+
+class BatchSolver:
+    """Many images of independent sizes, alphas and curvature kinds in packed float32 buffers.
+
+    ``specs`` is a list of dicts with keys height, width, alpha, kind (0 mean, 1 Gaussian) and
+    optionally levels.  Use :meth:`pack` / :meth:`unpack` to move between the packed device
+    buffer and per-image 2-D views."""
+
+    def __init__(self, specs, samples: int = 16, bisections: int = 32, stream=None):
+        n = len(specs)
+        arr = (MgCurvParams * n)()
+        for i, sp in enumerate(specs):
+            p = default_params(int(sp["height"]), int(sp["width"]), alpha=float(sp["alpha"]),
+                               curvature=int(sp.get("kind", 0)), levels=int(sp.get("levels", 0)),
+                               state_dtype=MG_F32, fine_colours=4, samples=samples, bisections=bisections)
+            arr[i] = p
+        self.n = n
+        self.specs = [dict(sp) for sp in specs]
+        self.b = C.c_void_p()
+        _bcheck(lib.mg_curv_batch_init(arr, n, C.c_void_p(_stream_handle(stream)), C.byref(self.b)))
+        self.offsets = [lib.mg_curv_batch_offset(self.b, i) for i in range(n + 1)]
+        self.total = self.offsets[-1]
+        self.levels = lib.mg_curv_batch_levels(self.b)
+
+    def close(self):
+        if self.b:
+            lib.mg_curv_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, images) -> torch.Tensor:
+        out = torch.empty(self.total, dtype=torch.float32, device="cuda")
+        for i, im in enumerate(images):
+            t = torch.as_tensor(im, dtype=torch.float32)
+            out[self.offsets[i]:self.offsets[i + 1]].copy_(t.reshape(-1))
+        return out
+
+    def unpack(self, packed: torch.Tensor):
+        return [packed[self.offsets[i]:self.offsets[i + 1]].view(self.specs[i]["height"], self.specs[i]["width"])
+                for i in range(self.n)]
+
+    def _ptr(self, t: torch.Tensor, name: str) -> int:
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != self.total:
+            raise ValueError(f"{name} must be a contiguous float32 device tensor of {self.total} elements")
+        return t.data_ptr()
+
+    def vcycle(self, u, f, want_energy: bool = False):
+        e = (C.c_double * self.n)() if want_energy else None
+        _bcheck(lib.mg_curv_batch_vcycle(self.b, self._ptr(u, "u"), self._ptr(f, "f"), e), self.b)
+        return list(e) if want_energy else None
+
+    def level(self, u, f, level: int):
+        _bcheck(lib.mg_curv_batch_level(self.b, self._ptr(u, "u"), self._ptr(f, "f"), level), self.b)
+
+    def sweep(self, u, f, level: int, colour: int):
+        _bcheck(lib.mg_curv_batch_sweep(self.b, self._ptr(u, "u"), self._ptr(f, "f"), level, colour), self.b)
+
+    def energy(self, u, f):
+        e = (C.c_double * self.n)()
+        _bcheck(lib.mg_curv_batch_energy(self.b, self._ptr(u, "u"), self._ptr(f, "f"), e), self.b)
+        return list(e)
+
+    def solve(self, u, f, rel_tol: float = 1e-6, max_vcycles: int = 1000):
+        done = (C.c_int32 * self.n)()
+        fin = (C.c_double * self.n)()
+        st = (C.c_int32 * self.n)()
+        s = _bcheck(lib.mg_curv_batch_solve(self.b, self._ptr(u, "u"), self._ptr(f, "f"), rel_tol, max_vcycles,
+                                            done, fin, st), self.b)
+        return {"status": s, "vcycles": list(done), "energy": list(fin), "image_status": list(st)}
+
+    def tune(self, u, f, repeats: int = 2):
+        _bcheck(lib.mg_curv_batch_tune(self.b, self._ptr(u, "u"), self._ptr(f, "f"), repeats), self.b)
+
+    def config(self, level: int):
+        g, r, gr = C.c_int32(), C.c_int32(), C.c_int32()
+        lib.mg_curv_batch_config(self.b, level, C.byref(g), C.byref(r), C.byref(gr))
+        return {"group": g.value, "records": r.value, "grid": gr.value}
+
+    def set_config(self, level: int, group: int, records: int, grid: int):
+        _bcheck(lib.mg_curv_batch_set_config(self.b, level, group, records, grid), self.b)

@@ -1,0 +1,40 @@
+"""Shared checks for the GPU parity tests (teacher-forced comparison of one colour sweep)."""
+import numpy as np
+
+
+def _blocks_of(o, level, colour):
+    m, n = o.grid(level)
+    return [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
+
+
+def _check_sweep_against_oracle(o, f, before, after, level, colour, fp64=True):
+    """Teacher-forced parity of one colour sweep: the oracle solves every block of the colour from the
+    GPU's own input state.  A block passes if its correction matches to 1e-10 (FP64 state; in FP32 the
+    rounded block values must match), or, where the arg-min is ill-conditioned (a minimum on a kink of
+    |kappa| with a tiny slope), if the GPU's correction reaches the same local-energy minimum
+    (oracle's Delta at the GPU's c within 1e-12 (1 + V0) of the oracle's own).  Returns
+    (max |dc|, number of blocks that needed the equal-minimum criterion)."""
+    worst, n_equal = 0.0, 0
+    for p, q in _blocks_of(o, level, colour):
+        bnd = o.block_bounds(level, p, q)
+        r0, r1, c0, c1 = bnd
+        info = o.local_solve(before, f, bnd)
+        c_gpu = after[r0, c0] - before[r0, c0]
+        if fp64:
+            dc = abs(c_gpu - info.c)
+            ok = dc <= 1e-10
+        else:
+            expect = (before[r0:r1, c0:c1] + info.c).astype(np.float32).astype(np.float64)
+            dc = float(np.max(np.abs(after[r0:r1, c0:c1] - expect)))
+            ok = dc == 0.0
+        # every pixel of the block moved by the same c
+        assert np.allclose(after[r0:r1, c0:c1] - before[r0:r1, c0:c1], c_gpu, rtol=0, atol=1e-6 if not fp64 else 1e-13)
+        if not ok:
+            v0 = info.K0 + 0.5 * o.p.alpha * info.s * info.fs ** 2
+            d_gpu = o.local_delta(before, f, bnd, c_gpu)
+            d_orc = o.local_delta(before, f, bnd, info.c)
+            assert d_gpu <= d_orc + 1e-12 * (1 + v0) + (0 if fp64 else 1e-7 * (1 + v0)), \
+                (level, colour, p, q, c_gpu, info.c, d_gpu, d_orc)
+            n_equal += 1
+        worst = max(worst, dc)
+    return worst, n_equal

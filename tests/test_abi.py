@@ -30,7 +30,8 @@ def lib():
     L.mg_curv_last_error.restype = C.c_char_p
     L.mg_curv_last_error.argtypes = [C.c_void_p]
     L.mg_curv_default_params.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32]
-    for name in ("mg_curv_vcycle", "mg_curv_energy", "mg_curv_sweep", "mg_curv_solve", "mg_curv_level"):
+    for name in ("mg_curv_vcycle", "mg_curv_energy", "mg_curv_sweep", "mg_curv_solve", "mg_curv_level",
+                 "mg_curv_batch_init", "mg_curv_batch_vcycle", "mg_curv_batch_solve"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -95,3 +96,49 @@ def test_no_device_reports_device_error(lib):
     ctx = C.c_void_p()
     assert lib.mg_curv_init(C.byref(p), None, C.byref(ctx)) == -5
     assert b"device" in lib.mg_curv_last_error(None).lower()
+
+
+def _batch_params(lib, shapes, **over):
+    arr = (Params * len(shapes))()
+    for i, (h, w) in enumerate(shapes):
+        lib.mg_curv_default_params(C.byref(arr[i]), h, w)
+        for k, v in over.items():
+            setattr(arr[i], k, v)
+    return arr
+
+
+@pytest.mark.parametrize("over,status", [
+    ({"state_dtype": 1}, -3), ({"fine_colours": 9}, -1), ({"height": 1}, -2), ({"alpha": -1.0}, -1),
+    ({"curvature": 5}, -1),
+])
+def test_batch_invalid_params(lib, over, status):
+    lib.mg_curv_batch_init.restype = C.c_int
+    lib.mg_curv_batch_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.mg_curv_batch_last_error.restype = C.c_char_p
+    arr = _batch_params(lib, [(32, 40), (64, 64)], **over)
+    b = C.c_void_p()
+    assert lib.mg_curv_batch_init(arr, 2, None, C.byref(b)) == status
+    assert not b.value
+    assert lib.mg_curv_batch_last_error(None)
+
+
+def test_batch_mismatched_search_constants_and_empty(lib):
+    lib.mg_curv_batch_init.restype = C.c_int
+    lib.mg_curv_batch_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    arr = _batch_params(lib, [(32, 40), (64, 64)])
+    arr[1].samples = 8
+    b = C.c_void_p()
+    assert lib.mg_curv_batch_init(arr, 2, None, C.byref(b)) == -1
+    assert lib.mg_curv_batch_init(arr, 0, None, C.byref(b)) == -1
+    assert lib.mg_curv_batch_init(None, 2, None, C.byref(b)) == -1
+
+
+def test_batch_no_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib.mg_curv_batch_init.restype = C.c_int
+    lib.mg_curv_batch_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    arr = _batch_params(lib, [(32, 40), (64, 64)])
+    b = C.c_void_p()
+    assert lib.mg_curv_batch_init(arr, 2, None, C.byref(b)) == -5

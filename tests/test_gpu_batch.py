@@ -1,0 +1,218 @@
+"""GPU tests of the batched path: many images of different sizes, alphas and curvature kinds.
+
+Parity chain: (1) with the default lane-group shapes the batch reproduces single-image runs
+bit for bit (same device solvers, same shapes), and the single-image path is checked against
+the oracle in test_gpu_parity.py; (2) independently, every image of a batch is checked
+against the oracle sweep by sweep from the batch's own state, also after autotuning (which
+only changes summation order); (3) the graph-replayed solve equals eager V-cycles bit for
+bit; (4) the full 256-image mixed workload is checked on sampled blocks."""
+import numpy as np
+import pytest
+import torch
+
+from synth import batch_specs, noisy_image
+from tests.parity_helpers import _check_sweep_against_oracle
+
+pytestmark = pytest.mark.gpu
+
+THREADS = 8
+
+SMALL = [  # (H, W, alpha, kind)
+    (40, 56, 20.0, 0), (64, 64, 10.0, 1), (33, 47, 40.0, 0), (130, 96, 20.0, 1),
+    (96, 130, 20.0, 0), (2, 3, 20.0, 0), (72, 72, 40.0, 1), (200, 150, 10.0, 0),
+]
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2204_07921_amd import mgcurv
+    return mgcurv
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _images(shapes, seed0=300):
+    fs = []
+    for k, (h, w, a, kind) in enumerate(shapes):
+        f, _ = noisy_image(h, w, seed0 + k, 0.03 + 0.09 * ((k * 37) % 10) / 10, dtype=np.float32)
+        fs.append(f)
+    return fs
+
+
+def _specs(shapes):
+    return [dict(height=h, width=w, alpha=a, kind=k) for h, w, a, k in shapes]
+
+
+def test_batch_matches_single_images_bitwise(mg):
+    _case("batch vs single images, 3 V-cycles")
+    fs = _images(SMALL)
+    bs = mg.BatchSolver(_specs(SMALL))
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    for _ in range(3):
+        bs.vcycle(ud, fd)
+    e_batch = bs.energy(ud, fd)
+    outs = bs.unpack(ud)
+    for k, (h, w, a, kind) in enumerate(SMALL):
+        s = mg.Solver(h, w, alpha=a, kind=kind, dtype=torch.float32)
+        f1 = torch.tensor(fs[k], device="cuda")
+        u1 = f1.clone()
+        for _ in range(3):
+            s.vcycle(u1, f1)
+        assert torch.equal(outs[k], u1), k
+        e1 = s.energy(u1, f1)
+        assert abs(e1 - e_batch[k]) <= 2.2e-16 * h * w * abs(e1) + 1e-300, (k, e1, e_batch[k])
+
+
+def _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, levels):
+    oracles = [orc.Oracle(sp["height"], sp["width"], sp["alpha"], sp["kind"], round_f32=True, threads=THREADS)
+               for sp in bs.specs]
+    f64 = [f.astype(np.float64) for f in fs]
+    for level in levels:
+        if level == 1:
+            # the pixel level runs all four colours in one call; check colour by colour through
+            # the oracle's Jacobi semantics by composing its four sweeps
+            before = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            bs.level(ud, fd, 1)
+            after = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            for k, o in enumerate(oracles):
+                if level > o.levels:
+                    continue
+                x = before[k].copy()
+                for colour in range(4):
+                    o.sweep(x, f64[k], 1, colour)
+                # composed over four colours; an FP64 rounding tie may move one float by an ulp
+                diff = np.abs(x - after[k])
+                assert diff.max() <= 1e-5 and np.count_nonzero(diff) <= max(1, diff.size // 1000), k
+            continue
+        for colour in range(4):
+            before = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            bs.sweep(ud, fd, level, colour)
+            after = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            for k, o in enumerate(oracles):
+                if level > o.levels:
+                    assert np.array_equal(before[k], after[k])
+                    continue
+                _, n_equal = _check_sweep_against_oracle(o, f64[k], before[k], after[k], level, colour, fp64=False)
+                assert n_equal <= 1, (k, level, colour)
+
+
+def test_batch_sweeps_match_oracle(mg, orc):
+    _case("batch sweeps vs oracle")
+    fs = _images(SMALL)
+    bs = mg.BatchSolver(_specs(SMALL))
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    bs.vcycle(ud, fd)
+    _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, range(1, bs.levels + 1))
+
+
+def test_batch_tuned_sweeps_match_oracle(mg, orc):
+    _case("tuned batch sweeps vs oracle")
+    fs = _images(SMALL)
+    bs = mg.BatchSolver(_specs(SMALL))
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    bs.tune(ud, fd, repeats=1)
+    assert torch.equal(ud, fd)  # tuning does not modify u
+    cfgs = [bs.config(l) for l in range(1, bs.levels + 1)]
+    print("tuned:", cfgs)
+    bs.vcycle(ud, fd)
+    _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, range(1, bs.levels + 1))
+
+
+def test_every_compiled_shape_matches_oracle(mg, orc):
+    """Force each compiled lane-group shape of a level and check that level against the oracle."""
+    shapes = [(130, 150, 20.0, 0), (150, 130, 20.0, 1), (97, 64, 10.0, 0)]
+    fs = _images(shapes, seed0=500)
+    cands = {2: [(16, 1), (8, 2), (4, 4)], 3: [(32, 1), (16, 2), (8, 4)], 4: [(64, 1), (32, 2), (16, 4)],
+             5: [(64, 2), (32, 4)], 6: [(64, 4), (32, 8)], 7: [(256, 2), (128, 4), (64, 8)], 8: [(256, 4), (512, 2)]}
+    for level, shs in cands.items():
+        for g, r in shs:
+            _case(f"shape level={level} group={g} records={r}")
+            bs = mg.BatchSolver(_specs(shapes))
+            bs.set_config(level, g, r, 1024)
+            fd = bs.pack(fs)
+            ud = fd.clone()
+            _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, [level])
+
+
+def test_graph_solve_equals_eager_vcycles(mg):
+    _case("graph replay vs eager")
+    fs = _images(SMALL)
+    bs = mg.BatchSolver(_specs(SMALL))
+    fd = bs.pack(fs)
+    ug = fd.clone()
+    res = bs.solve(ug, fd, rel_tol=0.0, max_vcycles=4)
+    assert res["vcycles"] == [4] * len(SMALL)
+    ue = fd.clone()
+    for _ in range(4):
+        torch.cuda.synchronize()
+        bs.vcycle(ue, fd)
+    assert torch.equal(ug, ue)
+    assert res["energy"] == bs.energy(ue, fd)
+
+
+def test_batch_solve_per_image_convergence(mg):
+    """Each image stops at its own relative-energy criterion with the same V-cycle count and status
+    as a single-image solve (one of these images creeps at ~1.4e-6 relative per cycle and does not
+    reach 1e-6 within 400 cycles, in the oracle too); a constant image converges after one cycle and
+    stays constant."""
+    _case("per-image convergence")
+    shapes = SMALL[:5] + [(48, 40, 20.0, 1)]
+    fs = _images(shapes)
+    fs[-1] = np.full((48, 40), 0.25, dtype=np.float32)
+    bs = mg.BatchSolver(_specs(shapes))
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    res = bs.solve(ud, fd, rel_tol=1e-6, max_vcycles=400)
+    outs = bs.unpack(ud)
+    assert res["status"] == (0 if all(st == 0 for st in res["image_status"]) else 1)
+    for k, (h, w, a, kind) in enumerate(shapes):
+        s = mg.Solver(h, w, alpha=a, kind=kind, dtype=torch.float32)
+        f1 = torch.tensor(fs[k], device="cuda")
+        u1 = f1.clone()
+        r1 = s.solve(u1, f1, rel_tol=1e-6, max_vcycles=400)
+        assert res["vcycles"][k] == r1["vcycles"], (k, res["vcycles"][k], r1["vcycles"])
+        assert res["image_status"][k] == r1["status"], k
+        assert torch.equal(outs[k], u1), k
+    assert res["vcycles"][-1] == 1
+    assert torch.all(outs[-1] == 0.25)
+
+
+def test_full_mixed_batch_sampled(mg, orc):
+    """256 images, sizes from {128..1024}^2 (non-square allowed), sigma ~ U[0.03, 0.12],
+    alpha in {10, 20, 40}, mixed kinds: two V-cycles, then sampled blocks of a few images and
+    levels against the oracle's local solve from the batch's own state."""
+    specs = batch_specs(256, seed=0)
+    _case(f"full batch: {sum(s['height'] * s['width'] for s in specs) / 1e6:.1f} Mpx")
+    fs = [noisy_image(s["height"], s["width"], s["seed"], s["sigma"], dtype=np.float32)[0] for s in specs]
+    bs = mg.BatchSolver(specs)
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    e0 = bs.energy(ud, fd)
+    e1 = bs.vcycle(ud, fd, want_energy=True)
+    e2 = bs.vcycle(ud, fd, want_energy=True)
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(e0, e1))
+    rng = np.random.default_rng(0)
+    picks = rng.choice(256, size=4, replace=False)
+    for level in (2, 4, 7):
+        colour = int(rng.integers(0, 4))
+        before = [bs.unpack(ud)[int(k)].cpu().numpy().astype(np.float64) for k in picks]
+        bs.sweep(ud, fd, level, colour)
+        after = [bs.unpack(ud)[int(k)].cpu().numpy().astype(np.float64) for k in picks]
+        for t, k in enumerate(picks):
+            sp = specs[int(k)]
+            o = orc.Oracle(sp["height"], sp["width"], sp["alpha"], sp["kind"], round_f32=True)
+            if level > o.levels:
+                continue
+            m, n = o.grid(level)
+            cand = [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
+            for j in rng.choice(len(cand), size=min(6, len(cand)), replace=False):
+                p, q = cand[int(j)]
+                r0, r1, c0, c1 = o.block_bounds(level, p, q)
+                info = o.local_solve(before[t], fs[int(k)].astype(np.float64), (r0, r1, c0, c1))
+                expect = (before[t][r0:r1, c0:c1] + info.c).astype(np.float32).astype(np.float64)
+                assert np.max(np.abs(after[t][r0:r1, c0:c1] - expect)) <= 2.5e-7, (int(k), level, p, q)
