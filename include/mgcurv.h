@@ -192,6 +192,52 @@ mg_status mg_curv_batch_set_config(mg_curv_batch *b, int32_t level, int32_t grou
 void mg_curv_batch_destroy(mg_curv_batch *b);
 const char *mg_curv_batch_last_error(const mg_curv_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A six-layer CNN g (3x3 convolutions with zero "same"
+ * padding, channels 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, ReLU after the first
+ * five) predicts an initial state u0 = f + g(f) for the multigrid solve; it is
+ * trained by mean squared error against multigrid solutions with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Weights are FP32 masters with bfloat16
+ * copies; activations are stored in bfloat16; all sums accumulate in FP32.
+ * Parameter vector (float32, mg_cnn_num_params() = 37601 entries), layer by
+ * layer: W_l as (ky, kx, c_in, c_out) row-major, then b_l (c_out).
+ * Images are float32 device arrays of n x height x width (row-major); the
+ * context holds activation buffers for `max_pixels` = n * height * width.
+ * ------------------------------------------------------------------------ */
+typedef struct mg_cnn mg_cnn;
+
+int32_t mg_cnn_num_params(void);
+
+/* Allocate a network context for batches of up to max_pixels pixels
+ * (about 450 bytes of device memory per pixel).  Parameters start unset:
+ * call mg_cnn_set_params before use. */
+mg_status mg_cnn_init(int64_t max_pixels, void *hip_stream, mg_cnn **out);
+
+/* Copy parameters from a host array (and reset the Adam moments and step);
+ * read them back into a host array.  Both wait for completion. */
+mg_status mg_cnn_set_params(mg_cnn *c, const float *host_params);
+mg_status mg_cnn_get_params(mg_cnn *c, float *host_params);
+
+/* u = f + g(f) for n images (device pointers, u may not alias f).  Enqueued only. */
+mg_status mg_cnn_forward(mg_cnn *c, const float *f, float *u, int32_t n, int32_t height, int32_t width);
+
+/* One Adam step on the mean squared error of f + g(f) against target; *loss
+ * (nullable) receives the loss before the step (waits when non-null). */
+mg_status mg_cnn_train_step(mg_cnn *c, const float *f, const float *target, int32_t n, int32_t height, int32_t width,
+                            float lr, double *loss);
+
+/* Loss and parameter gradient (host array of mg_cnn_num_params floats,
+ * nullable) without updating the parameters.  Waits. */
+mg_status mg_cnn_gradients(mg_cnn *c, const float *f, const float *target, int32_t n, int32_t height, int32_t width,
+                           double *loss, float *host_grads);
+
+/* Copy the first `count` bfloat16 values of activation a_layer (layer 1..5,
+ * NHWC with 32 channels) of the last forward pass to a host buffer. */
+mg_status mg_cnn_activation(mg_cnn *c, int32_t layer, void *host_out, int64_t count);
+
+void mg_cnn_destroy(mg_cnn *c);
+const char *mg_cnn_last_error(const mg_cnn *c);
+
 #ifdef __cplusplus
 }
 #endif

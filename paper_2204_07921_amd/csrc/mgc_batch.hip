@@ -239,11 +239,12 @@ struct BlockCfg {
 
 static std::vector<BlockCfg> block_candidates(int b)
 {
+    // the first entry is the single-image path's shape for this block side
     switch (b) {
-    case 2: return {{16, 1}, {8, 2}, {4, 4}};
-    case 4: return {{32, 1}, {16, 2}, {8, 4}};
-    case 8: return {{64, 1}, {32, 2}, {16, 4}};
-    case 16: return {{64, 2}, {32, 4}};
+    case 2: return {{4, 4}, {16, 1}, {8, 2}, {2, 8}};
+    case 4: return {{8, 4}, {32, 1}, {16, 2}, {4, 8}};
+    case 8: return {{16, 4}, {64, 1}, {32, 2}, {8, 8}};
+    case 16: return {{32, 4}, {64, 2}, {16, 8}};
     case 32: return {{64, 4}, {32, 8}};
     case 64: return {{256, 2}, {128, 4}, {64, 8}};
     case 128: return {{256, 4}, {512, 2}};
@@ -272,10 +273,10 @@ static hipError_t launch_batch_blocks(hipStream_t s, BlockCfg cfg, int grid, flo
 #define MGC_CASE(GR, RP, LZ)                                                                                     \
     if (cfg.group == GR && cfg.rpl == RP && lazy == LZ)                                                          \
         return launch_bb<GR, RP, LZ>(s, grid, u, f, imgs, order, cum, n, total, active, a, M, G);
-    MGC_CASE(16, 1, false) MGC_CASE(8, 2, false) MGC_CASE(4, 4, false)
-    MGC_CASE(32, 1, false) MGC_CASE(16, 2, false) MGC_CASE(8, 4, false)
-    MGC_CASE(64, 1, false) MGC_CASE(32, 2, false) MGC_CASE(16, 4, false)
-    MGC_CASE(64, 2, false) MGC_CASE(32, 4, false)
+    MGC_CASE(16, 1, false) MGC_CASE(8, 2, false) MGC_CASE(4, 4, false) MGC_CASE(2, 8, false)
+    MGC_CASE(32, 1, false) MGC_CASE(16, 2, false) MGC_CASE(8, 4, false) MGC_CASE(4, 8, false)
+    MGC_CASE(64, 1, false) MGC_CASE(32, 2, false) MGC_CASE(16, 4, false) MGC_CASE(8, 8, false)
+    MGC_CASE(64, 2, false) MGC_CASE(32, 4, false) MGC_CASE(16, 8, false)
     MGC_CASE(64, 4, false) MGC_CASE(32, 8, false)
     MGC_CASE(256, 2, true) MGC_CASE(128, 4, true) MGC_CASE(64, 8, true)
     MGC_CASE(256, 4, true) MGC_CASE(512, 2, true)

@@ -177,7 +177,7 @@ static hipError_t launch_blocks_cfg(const LaunchCtx& L, void* u, const void* f, 
     if (groups == 0) return hipSuccess;
     dim3 grid, block;
     if (GROUP <= 64) {
-        block = dim3(256);
+        block = dim3(256);  // several lane groups per workgroup
         grid = dim3((unsigned)(((size_t)groups * GROUP + 255) / 256));
     } else {
         block = dim3(GROUP);
@@ -192,12 +192,13 @@ template <typename T, int KIND>
 static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr,
                                   int nbc, const CoarseArgs& ca)
 {
-    // ring size of an unclipped block is 8b
+    // ring size of an unclipped block is 8b; shapes are the fastest of the batched autotuner's
+    // candidates on the 1024x1024 and mixed-size workloads (fewer lanes, more records per lane)
     switch (b) {
-    case 2: return launch_blocks_cfg<T, KIND, 16, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    case 4: return launch_blocks_cfg<T, KIND, 32, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    case 8: return launch_blocks_cfg<T, KIND, 64, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    case 16: return launch_blocks_cfg<T, KIND, 64, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 2: return launch_blocks_cfg<T, KIND, 4, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 4: return launch_blocks_cfg<T, KIND, 8, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 8: return launch_blocks_cfg<T, KIND, 16, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 16: return launch_blocks_cfg<T, KIND, 32, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 32: return launch_blocks_cfg<T, KIND, 64, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 64: return launch_blocks_cfg<T, KIND, 256, 2, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 128: return launch_blocks_cfg<T, KIND, 256, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);

@@ -86,6 +86,26 @@ def _load() -> C.CDLL:
     L.mg_curv_batch_last_error.argtypes = [vp]
     L.mg_curv_levels.restype = C.c_int32
     L.mg_curv_levels.argtypes = [vp]
+    L.mg_cnn_num_params.restype = C.c_int32
+    L.mg_cnn_num_params.argtypes = []
+    L.mg_cnn_init.restype = C.c_int
+    L.mg_cnn_init.argtypes = [C.c_int64, vp, C.POINTER(vp)]
+    L.mg_cnn_set_params.restype = C.c_int
+    L.mg_cnn_set_params.argtypes = [vp, vp]
+    L.mg_cnn_get_params.restype = C.c_int
+    L.mg_cnn_get_params.argtypes = [vp, vp]
+    L.mg_cnn_forward.restype = C.c_int
+    L.mg_cnn_forward.argtypes = [vp, cvp, vp, C.c_int32, C.c_int32, C.c_int32]
+    L.mg_cnn_train_step.restype = C.c_int
+    L.mg_cnn_train_step.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.POINTER(C.c_double)]
+    L.mg_cnn_gradients.restype = C.c_int
+    L.mg_cnn_gradients.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+    L.mg_cnn_activation.restype = C.c_int
+    L.mg_cnn_activation.argtypes = [vp, C.c_int32, vp, C.c_int64]
+    L.mg_cnn_destroy.restype = None
+    L.mg_cnn_destroy.argtypes = [vp]
+    L.mg_cnn_last_error.restype = C.c_char_p
+    L.mg_cnn_last_error.argtypes = [vp]
     L.mg_curv_destroy.restype = None
     L.mg_curv_destroy.argtypes = [vp]
     L.mg_curv_last_error.restype = C.c_char_p
@@ -317,3 +337,86 @@ class BatchSolver:
 
     def set_config(self, level: int, group: int, records: int, grid: int):
         _bcheck(lib.mg_curv_batch_set_config(self.b, level, group, records, grid), self.b)
+
+
+# --- warm-start CNN ---------------------------------------------------------------
+
+def _ccheck(status: int, c=None) -> int:
+    if status < 0:
+        raise MgCurvError(status, lib.mg_cnn_last_error(c).decode())
+    return status
+
+
+class WarmStartCNN:
+    """The six-layer warm-start network (bfloat16 MFMA kernels in libmgcurv.so).
+
+    Images are float32 device tensors of shape (n, height, width)."""
+
+    def __init__(self, max_pixels: int, params=None, stream=None):
+        self.c = C.c_void_p()
+        _ccheck(lib.mg_cnn_init(int(max_pixels), C.c_void_p(_stream_handle(stream)), C.byref(self.c)))
+        self.n_params = lib.mg_cnn_num_params()
+        self.max_pixels = int(max_pixels)
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if self.c:
+            lib.mg_cnn_destroy(self.c)
+            self.c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        _ccheck(lib.mg_cnn_set_params(self.c, p.ctypes.data), self.c)
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(self.n_params, dtype=np.float32)
+        _ccheck(lib.mg_cnn_get_params(self.c, p.ctypes.data), self.c)
+        return p
+
+    @staticmethod
+    def _img(t: torch.Tensor, name: str):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 3:
+            raise ValueError(f"{name} must be a contiguous float32 device tensor (n, height, width)")
+        return t.data_ptr()
+
+    def forward(self, f: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+        n, h, w = f.shape
+        u = torch.empty_like(f) if out is None else out
+        _ccheck(lib.mg_cnn_forward(self.c, self._img(f, "f"), self._img(u, "u"), n, h, w), self.c)
+        return u
+
+    def train_step(self, f: torch.Tensor, target: torch.Tensor, lr: float, want_loss: bool = True):
+        n, h, w = f.shape
+        loss = C.c_double()
+        _ccheck(lib.mg_cnn_train_step(self.c, self._img(f, "f"), self._img(target, "target"), n, h, w, float(lr),
+                                      C.byref(loss) if want_loss else None), self.c)
+        return loss.value if want_loss else None
+
+    def gradients(self, f: torch.Tensor, target: torch.Tensor):
+        import numpy as np
+        n, h, w = f.shape
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        _ccheck(lib.mg_cnn_gradients(self.c, self._img(f, "f"), self._img(target, "target"), n, h, w,
+                                     C.byref(loss), g.ctypes.data), self.c)
+        return loss.value, g
+
+    def activation(self, layer: int, shape):
+        """Activation a_layer (1..5) of the last forward pass as float32 numpy (n, h, w, 32)."""
+        import numpy as np
+        n, h, w = shape
+        count = n * h * w * 32
+        raw = np.empty(count, dtype=np.uint16)
+        _ccheck(lib.mg_cnn_activation(self.c, layer, raw.ctypes.data, count), self.c)
+        return (raw.astype(np.uint32) << 16).view(np.float32).reshape(n, h, w, 32)

@@ -1,0 +1,138 @@
+"""GPU tests of the warm-start CNN against the FP64 NumPy reference (oracle/cnn_ref.py).
+
+Tolerances follow from bfloat16 storage: both sides round weights, activations and activation
+gradients to bfloat16 at the same points (round to nearest even); the GPU accumulates in FP32,
+the reference in FP64, so a stored value can land one bfloat16 step (2^-8 relative) away when
+the two accumulations straddle a rounding boundary.  Layers are compared from the GPU's own
+inputs (teacher forcing) so such steps do not compound; gradients are compared by relative
+norm and direction per layer."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn_ref
+from synth import init_params, noisy_image
+
+pytestmark = pytest.mark.gpu
+
+LAYER_SLICES = []
+_k = 0
+for _ci, _co in zip(cnn_ref.CHANNELS[:-1], cnn_ref.CHANNELS[1:]):
+    LAYER_SLICES.append(slice(_k, _k + 9 * _ci * _co + _co))
+    _k += 9 * _ci * _co + _co
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2204_07921_amd import mgcurv
+    return mgcurv
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _batch(shapes, seed=0):
+    fs = [noisy_image(h, w, seed + k, 0.08, dtype=np.float32)[0] for k, (h, w) in enumerate(shapes)]
+    return fs
+
+
+def _params(seed, scale=2.0):
+    p = init_params(seed)
+    p *= scale          # larger weights: ReLUs switch inside the test images
+    p[LAYER_SLICES[-1]] *= 5.0
+    for sl in LAYER_SLICES:  # non-zero biases exercise the bias paths
+        stop = sl.stop
+        co = 32 if sl is not LAYER_SLICES[-1] else 1
+        p[stop - co:stop] = 0.05 * np.cos(np.arange(co))
+    return p.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(2, 20, 40), (1, 9, 45), (3, 33, 17)])
+def test_forward_per_layer_matches_reference(mg, shape):
+    n, h, w = shape
+    _case(f"forward {shape}")
+    f = np.stack(_batch([(h, w)] * n))
+    p = _params(1)
+    net = mg.WarmStartCNN(n * h * w, p)
+    fd = torch.tensor(f, device="cuda")
+    u = net.forward(fd).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    layers = cnn_ref.unpack(p)
+    a = f[..., None].astype(np.float64)
+    for l in range(5):
+        W, b = layers[l]
+        ref = cnn_ref.round_bf16(np.maximum(cnn_ref.conv(a, cnn_ref.round_bf16(W), b), 0.0))
+        got = net.activation(l + 1, (n, h, w)).astype(np.float64)
+        step = 2.0 ** -7 * np.maximum(np.abs(ref), 1e-30)   # one bfloat16 step at the value
+        bad = np.abs(got - ref) > step + 1e-4 * np.max(np.abs(ref))
+        assert np.count_nonzero(bad) == 0, (l, np.max(np.abs(got - ref)))
+        a = got                                             # teacher forcing
+    W5, b5 = layers[5]
+    ref_u = f + cnn_ref.conv(a, cnn_ref.round_bf16(W5), b5)[..., 0]
+    assert np.max(np.abs(u - ref_u)) <= 1e-5 * (1 + np.max(np.abs(ref_u - f)))
+
+
+def test_gradients_match_reference(mg):
+    n, h, w = 2, 24, 40
+    _case("gradients")
+    f = np.stack(_batch([(h, w)] * n, seed=10))
+    target = (f + 0.05 * np.sin(np.arange(w))[None, None, :]).astype(np.float32)
+    p = _params(2)
+    net = mg.WarmStartCNN(n * h * w, p)
+    loss_g, g = net.gradients(torch.tensor(f, device="cuda"), torch.tensor(target, device="cuda"))
+    loss_r, gr = cnn_ref.loss_and_grad(p, f.astype(np.float64), target.astype(np.float64), bf16=True)
+    assert abs(loss_g - loss_r) <= 1e-3 * loss_r, (loss_g, loss_r)
+    for l, sl in enumerate(LAYER_SLICES):
+        a, b = g[sl].astype(np.float64), gr[sl]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        print(f"layer {l}: relative gradient error {rel:.2e}, cosine {cos:.6f}")
+        assert rel <= 2e-2 and cos >= 0.9995, (l, rel, cos)
+
+
+def test_adam_step_matches_reference(mg):
+    n, h, w = 1, 16, 32
+    _case("adam")
+    f = np.stack(_batch([(h, w)], seed=20))
+    target = (f * 0.9).astype(np.float32)
+    p = _params(3)
+    net = mg.WarmStartCNN(n * h * w, p)
+    fd, td = torch.tensor(f, device="cuda"), torch.tensor(target, device="cuda")
+    w64, m, v = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    for t in (1, 2):
+        _, g = net.gradients(fd, td)
+        net.train_step(fd, td, lr=1e-3, want_loss=False)
+        w64, m, v = cnn_ref.adam_step(w64, g.astype(np.float64), m, v, t, lr=1e-3)
+        got = net.get_params().astype(np.float64)
+        assert np.max(np.abs(got - w64)) <= 1e-6, t
+        w64 = got  # continue from the GPU's float32 state
+
+
+def test_training_reduces_loss_and_is_deterministic(mg):
+    _case("training")
+    n, h, w = 8, 32, 32
+    rng = np.random.default_rng(0)
+    f = np.stack(_batch([(h, w)] * n, seed=30))
+    # a smooth target: the 3x3 box mean of f (a learnable denoiser)
+    fp = np.pad(f, ((0, 0), (1, 1), (1, 1)), mode="edge")
+    target = sum(fp[:, dy:dy + h, dx:dx + w] for dy in range(3) for dx in range(3)) / 9.0
+    target = target.astype(np.float32)
+    fd, td = torch.tensor(f, device="cuda"), torch.tensor(target, device="cuda")
+    runs = []
+    for _ in range(2):
+        net = mg.WarmStartCNN(n * h * w, init_params(7))
+        losses = [net.train_step(fd, td, lr=2e-3) for _ in range(150)]
+        runs.append(net.get_params())
+        print(f"loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+        assert losses[-1] < 0.3 * losses[0]
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_input_validation(mg):
+    net = mg.WarmStartCNN(1000, init_params(0))
+    f = torch.zeros(2, 30, 30, device="cuda")
+    with pytest.raises(mg.MgCurvError):
+        net.forward(f)          # 1800 pixels > capacity 1000
+    with pytest.raises(ValueError):
+        net.set_params(np.zeros(10))
