@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-image batched measurement")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-solve", action="store_true", help="also solve all 256 images to 1e-6")
+    ap.add_argument("--no-warm", action="store_true", help="skip the CNN warm-start comparison")
+    ap.add_argument("--warm-batch", type=int, default=0,
+                    help="also compare plain and warm-started batched solves on this many 1024x1024 images")
     return ap.parse_args()
 
 
@@ -84,6 +87,46 @@ def measured_traffic(workload_key: str, kernel_prefix: str):
         if name.startswith(kernel_prefix):
             return int(round((k["fetch_kib"] + k["write_kib"]) * 1024))
     return None
+
+
+def warm_start_measure(fd, plain: dict, warm_batch: int) -> dict:
+    """Time-to-energy-tol at 1024x1024 with the learned warm start: CNN forward (u0 = f + g(f)),
+    then V-cycles until F <= F_plain (1 + 1e-6); if the budget (3x the plain V-cycles) runs out,
+    the plain solve from u0 = f is run as the fallback and its time is added."""
+    import torch
+    from paper_2204_07921_amd import mgcurv, warmstart
+    if not os.path.exists(warmstart.DEFAULT_WEIGHTS):
+        return {"skipped": "no trained weights"}
+    params, meta = warmstart.load()
+    net = mgcurv.WarmStartCNN(H * W, params)
+    solver = mgcurv.Solver(H, W, alpha=ALPHA, kind=0, dtype=torch.float32)
+    target = plain["final_energy"] * (1 + 1e-6)
+    f3 = fd.view(1, H, W)
+    u0 = torch.empty_like(f3)
+    net.forward(f3, u0)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    net.forward(f3, u0)
+    res = solver.solve_target(u0.view(H, W), fd, target, max_vcycles=3 * plain["vcycles"] + 1)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t
+    fallback = res["status"] != 0
+    if fallback:
+        uu = fd.clone()
+        t = time.perf_counter()
+        solver.solve(uu, fd, rel_tol=1e-6, max_vcycles=2000)
+        torch.cuda.synchronize()
+        t_warm += time.perf_counter() - t
+    out = {"weights": os.path.relpath(warmstart.DEFAULT_WEIGHTS, ROOT), "trained_on": {k: meta.get(k) for k in ("pairs", "size", "steps", "batch", "alpha", "kind")},
+           "plain_seconds": plain["seconds"], "plain_vcycles": plain["vcycles"], "plain_energy": plain["final_energy"],
+           "warm_seconds": round(t_warm, 4), "warm_vcycles": res["vcycles"], "warm_energy": res["energy"],
+           "fallback": fallback, "energy_gap_rel": (res["energy"] - plain["final_energy"]) / plain["final_energy"],
+           "speedup": round(plain["seconds"] / t_warm, 3)}
+    if warm_batch:
+        fe = warmstart.make_inputs(warm_batch, H, seed0=100000)
+        net8 = mgcurv.WarmStartCNN(8 * H * W, params)
+        out["batch"] = warmstart.evaluate(net8, fe)
+    return out
 
 
 def batch_measure(steps: int, solve: bool) -> dict:
@@ -242,6 +285,8 @@ def main():
         "energy_last": energies[-1],
         "time_to_tol": solves,
     }
+    if not args.no_warm and "mean" in solves:
+        out["warm_start"] = warm_start_measure(fd, solves["mean"], args.warm_batch)
     if not args.no_batch:
         out["batch"] = batch_measure(args.batch_steps, args.batch_solve)
     if not args.no_cpu:

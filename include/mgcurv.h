@@ -103,6 +103,13 @@ mg_status mg_curv_vcycle(mg_curv_ctx *ctx, void *u, const void *f, double *energ
 mg_status mg_curv_solve(mg_curv_ctx *ctx, void *u, const void *f, double rel_tol, int32_t max_vcycles,
                         int32_t *vcycles_done, double *final_energy, double *energy_trace);
 
+/* Run V-cycles on u until F(u) <= target_energy (checked before the first
+ * cycle as well) or max_vcycles cycles have run: the refinement step of a
+ * warm-started solve that must reach a given energy.  Returns MG_OK when the
+ * target was reached, MG_NOT_CONVERGED otherwise.  Outputs nullable. */
+mg_status mg_curv_solve_target(mg_curv_ctx *ctx, void *u, const void *f, double target_energy, int32_t max_vcycles,
+                               int32_t *vcycles_done, double *final_energy);
+
 /* F(u) of eq. MCM / GCM, accumulated in FP64 in a fixed order (the result is
  * bitwise reproducible for a given size and launch). */
 mg_status mg_curv_energy(mg_curv_ctx *ctx, const void *u, const void *f, double *energy);
@@ -176,6 +183,11 @@ mg_status mg_curv_batch_energy(mg_curv_batch *b, const void *u, const void *f, d
  * MG_NOT_CONVERGED otherwise (status[i] tells which), or an error. */
 mg_status mg_curv_batch_solve(mg_curv_batch *b, void *u, const void *f, double rel_tol, int32_t max_vcycles,
                               int32_t *vcycles_done, double *final_energy, int32_t *status);
+
+/* As mg_curv_batch_solve, but image i stops when F(u_i) <= target_energy[i]
+ * (host array of n doubles, checked before the first V-cycle too). */
+mg_status mg_curv_batch_solve_target(mg_curv_batch *b, void *u, const void *f, const double *target_energy,
+                                     int32_t max_vcycles, int32_t *vcycles_done, double *final_energy, int32_t *status);
 
 /* Autotune: for each level, time the compiled lane-group shapes and
  * persistent grid sizes on these buffers (u is not modified; a scratch copy

@@ -683,8 +683,12 @@ mg_status mg_curv_batch_energy(mg_curv_batch* b, const void* u, const void* f, d
     return MG_OK;
 }
 
-mg_status mg_curv_batch_solve(mg_curv_batch* b, void* u, const void* f, double rel_tol, int32_t max_vcycles,
-                              int32_t* vcycles_done, double* final_energy, int32_t* status)
+namespace {
+
+// Shared driver: stop image i when its relative energy change is below rel_tol (rel_tol > 0) or,
+// with targets, when its energy is at or below target[i] (checked before the first V-cycle too).
+mg_status batch_solve_impl(mg_curv_batch* b, void* u, const void* f, double rel_tol, const double* target,
+                           int32_t max_vcycles, int32_t* vcycles_done, double* final_energy, int32_t* status)
 {
     mg_status st = check_ptrs(b, u, f);
     if (st != MG_OK) return st;
@@ -693,13 +697,23 @@ mg_status mg_curv_batch_solve(mg_curv_batch* b, void* u, const void* f, double r
     if (e != hipSuccess) return bhip(b, e, "user stream synchronize");
     hipStream_t s = b->gstream;
     if ((st = set_all_active(b, s, 1)) != MG_OK) return st;
-    // E_0
     if ((st = batch_energy_enqueue(b, s, (const float*)u, (const float*)f)) != MG_OK) return st;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return bhip(b, e, "stream synchronize");
     std::vector<double> prev(b->e_host, b->e_host + b->n), cur(b->n);
-    for (int i = 0; i < b->n; ++i)
-        if (!std::isfinite(prev[i])) return bfail(b, MG_E_NONFINITE, "energy of image %d is not finite", i);
     std::vector<int> done(b->n, 0), conv(b->n, 0);
+    int remaining = b->n;
+    for (int i = 0; i < b->n; ++i) {
+        if (!std::isfinite(prev[i])) return bfail(b, MG_E_NONFINITE, "energy of image %d is not finite", i);
+        if (target && prev[i] <= target[i]) {
+            conv[i] = 1;
+            b->h_active[i] = 0;
+            --remaining;
+        }
+    }
+    if (remaining < b->n) {
+        e = hipMemcpyAsync(b->d_active, b->h_active.data(), sizeof(int) * b->n, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return bhip(b, e, "active flags");
+    }
     // capture one V-cycle + energies + host copy for these buffers
     drop_graph(b);
     if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) return bhip(b, e, "begin capture");
@@ -709,7 +723,6 @@ mg_status mg_curv_batch_solve(mg_curv_batch* b, void* u, const void* f, double r
     if (st != MG_OK) { drop_graph(b); return st; }
     if (e != hipSuccess) return bhip(b, e, "end capture");
     if ((e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return bhip(b, e, "graph instantiate");
-    int remaining = b->n;
     for (int l = 0; l < max_vcycles && remaining > 0; ++l) {
         if ((e = hipGraphLaunch(b->gexec, s)) != hipSuccess) return bhip(b, e, "graph launch");
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return bhip(b, e, "graph synchronize");
@@ -719,7 +732,9 @@ mg_status mg_curv_batch_solve(mg_curv_batch* b, void* u, const void* f, double r
             cur[i] = b->e_host[i];
             done[i] += 1;
             if (!std::isfinite(cur[i])) return bfail(b, MG_E_NONFINITE, "energy of image %d became non-finite", i);
-            if (rel_tol > 0.0 && (cur[i] == prev[i] || std::fabs(cur[i] - prev[i]) < rel_tol * std::fabs(cur[i]))) {
+            const bool stop = target ? cur[i] <= target[i]
+                                     : (rel_tol > 0.0 && (cur[i] == prev[i] || std::fabs(cur[i] - prev[i]) < rel_tol * std::fabs(cur[i])));
+            if (stop) {
                 conv[i] = 1;
                 b->h_active[i] = 0;
                 --remaining;
@@ -734,14 +749,30 @@ mg_status mg_curv_batch_solve(mg_curv_batch* b, void* u, const void* f, double r
     }
     if ((st = set_all_active(b, s, 1)) != MG_OK) return st;
     bool all_conv = true;
+    const bool has_criterion = target != nullptr || rel_tol > 0.0;
     for (int i = 0; i < b->n; ++i) {
         if (vcycles_done) vcycles_done[i] = done[i];
         if (final_energy) final_energy[i] = prev[i];
-        const int si = (rel_tol > 0.0 && !conv[i]) ? MG_NOT_CONVERGED : MG_OK;
+        const int si = (has_criterion && !conv[i]) ? MG_NOT_CONVERGED : MG_OK;
         if (status) status[i] = si;
         all_conv = all_conv && si == MG_OK;
     }
     return all_conv ? MG_OK : MG_NOT_CONVERGED;
+}
+
+}  // namespace
+
+mg_status mg_curv_batch_solve(mg_curv_batch* b, void* u, const void* f, double rel_tol, int32_t max_vcycles,
+                              int32_t* vcycles_done, double* final_energy, int32_t* status)
+{
+    return batch_solve_impl(b, u, f, rel_tol, nullptr, max_vcycles, vcycles_done, final_energy, status);
+}
+
+mg_status mg_curv_batch_solve_target(mg_curv_batch* b, void* u, const void* f, const double* target_energy,
+                                     int32_t max_vcycles, int32_t* vcycles_done, double* final_energy, int32_t* status)
+{
+    if (b && !target_energy) return bfail(b, MG_E_INVALID, "target_energy must be non-null");
+    return batch_solve_impl(b, u, f, 0.0, target_energy, max_vcycles, vcycles_done, final_energy, status);
 }
 
 mg_status mg_curv_batch_tune(mg_curv_batch* b, void* u, const void* f, int32_t repeats)

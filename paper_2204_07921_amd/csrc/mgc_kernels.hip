@@ -21,18 +21,42 @@ namespace mgc {
 // (2x2 cells for four colours, 3x3 for nine); the thread solves the cell's
 // pixel of the active colour and copies the cell's other pixels.
 // ---------------------------------------------------------------------------
+// Interior cells (every cell but the outer ring of cells): all their pixels
+// lie inside the image and off its border.
 template <typename T, int KIND, int NC>
 __global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                            const T* __restrict__ f, int H, int W, int colour,
                                                            int cells_r, int cells_c, double alpha, int M, int G)
 {
+    const int ir = cells_r - 2, ic = cells_c - 2;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= cells_r * cells_c) return;
-    const int cr = cell / cells_c, cc = cell - cr * cells_c;
-    solve_cell<T, KIND, NC>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
+    if (cell >= ir * ic) return;
+    const int cr = 1 + cell / ic, cc = 1 + cell % ic;
+    solve_cell<T, KIND, NC, 1>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
 }
 
-// Blocks of colour (pr, pc) at side b: block (p, q) = (2 bi + pr, 2 bj + pc), bi < nbr, bj < nbc.
+// The outer ring of cells (first and last cell row and column).
+template <typename T, int KIND, int NC>
+__global__ __launch_bounds__(256) void sweep_pixels_border_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                                  const T* __restrict__ f, int H, int W, int colour,
+                                                                  int cells_r, int cells_c, double alpha, int M, int G)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int cr, cc;
+    if (cells_r <= 2 || cells_c <= 2) {   // every cell is on the ring
+        if (k >= cells_r * cells_c) return;
+        cr = k / cells_c;
+        cc = k % cells_c;
+    } else {
+        if (k < cells_c) { cr = 0; cc = k; }
+        else if ((k -= cells_c) < cells_c) { cr = cells_r - 1; cc = k; }
+        else if ((k -= cells_c) < cells_r - 2) { cr = 1 + k; cc = 0; }
+        else if ((k -= cells_r - 2) < cells_r - 2) { cr = 1 + k; cc = cells_c - 1; }
+        else return;
+    }
+    solve_cell<T, KIND, NC, 0>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
+}
+
 template <typename T, int KIND, int GROUP, int RPL, bool LAZY>
 __global__ __launch_bounds__(GROUP > 64 ? GROUP : 256) void sweep_blocks_kernel(
     T* __restrict__ u, const T* __restrict__ f, int H, int W, int b, int pr, int pc, int nbr, int nbc,
@@ -144,19 +168,25 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restr
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+template <typename T, int KIND, int NC>
+static hipError_t launch_pixels_nc(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour)
+{
+    const int cells_r = (L.H + NC - 1) / NC, cells_c = (L.W + NC - 1) / NC;
+    const int n_in = (cells_r > 2 && cells_c > 2) ? (cells_r - 2) * (cells_c - 2) : 0;
+    const int n_border = cells_r * cells_c - n_in;
+    if (n_in > 0)
+        hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, NC>), dim3((n_in + 255) / 256), dim3(256), 0, L.stream,
+                           (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
+    hipLaunchKernelGGL((sweep_pixels_border_kernel<T, KIND, NC>), dim3((n_border + 255) / 256), dim3(256), 0, L.stream,
+                       (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
+    return hipGetLastError();
+}
+
 template <typename T, int KIND>
 static hipError_t launch_pixels_t(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int nc)
 {
-    const int cells_r = (L.H + nc - 1) / nc, cells_c = (L.W + nc - 1) / nc;
-    const int n = cells_r * cells_c;
-    dim3 grid((n + 255) / 256), block(256);
-    if (nc == 3)
-        hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, 3>), grid, block, 0, L.stream, (const T*)uin, (T*)uout,
-                           (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
-    else
-        hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, 2>), grid, block, 0, L.stream, (const T*)uin, (T*)uout,
-                           (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
-    return hipGetLastError();
+    return nc == 3 ? launch_pixels_nc<T, KIND, 3>(L, uin, uout, f, colour)
+                   : launch_pixels_nc<T, KIND, 2>(L, uin, uout, f, colour);
 }
 
 hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours)

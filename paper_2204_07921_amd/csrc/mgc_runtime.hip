@@ -302,6 +302,28 @@ mg_status mg_curv_solve(mg_curv_ctx* ctx, void* u, const void* f, double rel_tol
     return (rel_tol > 0.0 && !converged) ? MG_NOT_CONVERGED : MG_OK;
 }
 
+mg_status mg_curv_solve_target(mg_curv_ctx* ctx, void* u, const void* f, double target_energy, int32_t max_vcycles,
+                               int32_t* vcycles_done, double* final_energy)
+{
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    if (max_vcycles < 0 || std::isnan(target_energy)) return fail(ctx, MG_E_INVALID, "bad target_energy or max_vcycles");
+    double e;
+    st = energy(ctx, u, f, &e);
+    if (st != MG_OK) return st;
+    if (!std::isfinite(e)) return fail(ctx, MG_E_NONFINITE, "energy of the initial state is not finite");
+    int done = 0;
+    while (e > target_energy && done < max_vcycles) {
+        if ((st = vcycle(ctx, u, f)) != MG_OK) return st;
+        if ((st = energy(ctx, u, f, &e)) != MG_OK) return st;
+        ++done;
+        if (!std::isfinite(e)) return fail(ctx, MG_E_NONFINITE, "energy became non-finite after V-cycle %d", done);
+    }
+    if (vcycles_done) *vcycles_done = done;
+    if (final_energy) *final_energy = e;
+    return e <= target_energy ? MG_OK : MG_NOT_CONVERGED;
+}
+
 int32_t mg_curv_levels(const mg_curv_ctx* ctx) { return ctx ? ctx->J : 0; }
 
 void mg_curv_destroy(mg_curv_ctx* ctx)

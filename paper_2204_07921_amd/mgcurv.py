@@ -50,6 +50,11 @@ def _load() -> C.CDLL:
     L.mg_curv_solve.restype = C.c_int
     L.mg_curv_solve.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.POINTER(C.c_int32),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.mg_curv_solve_target.restype = C.c_int
+    L.mg_curv_solve_target.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.mg_curv_batch_solve_target.restype = C.c_int
+    L.mg_curv_batch_solve_target.argtypes = [vp, vp, cvp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_double), C.POINTER(C.c_int32)]
     L.mg_curv_energy.restype = C.c_int
     L.mg_curv_energy.argtypes = [vp, cvp, cvp, C.POINTER(C.c_double)]
     L.mg_curv_sweep.restype = C.c_int
@@ -184,6 +189,14 @@ def mg_curv_solve(ctx, params, u, f, rel_tol: float = 1e-6, max_vcycles: int = 1
     return out
 
 
+def mg_curv_solve_target(ctx, params, u, f, target_energy: float, max_vcycles: int = 1000):
+    done = C.c_int32()
+    fin = C.c_double()
+    st = _check(lib.mg_curv_solve_target(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"),
+                                         float(target_energy), max_vcycles, C.byref(done), C.byref(fin)), ctx)
+    return {"status": st, "vcycles": done.value, "energy": fin.value}
+
+
 def mg_curv_energy(ctx, params, u, f) -> float:
     e = C.c_double()
     _check(lib.mg_curv_energy(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), C.byref(e)), ctx)
@@ -237,6 +250,9 @@ class Solver:
 
     def energy(self, u, f):
         return mg_curv_energy(self.ctx, self.params, u, f)
+
+    def solve_target(self, u, f, target_energy, max_vcycles=1000):
+        return mg_curv_solve_target(self.ctx, self.params, u, f, target_energy, max_vcycles)
 
     def sweep(self, u, f, level, colour):
         return mg_curv_sweep(self.ctx, self.params, u, f, level, colour)
@@ -325,6 +341,15 @@ class BatchSolver:
         st = (C.c_int32 * self.n)()
         s = _bcheck(lib.mg_curv_batch_solve(self.b, self._ptr(u, "u"), self._ptr(f, "f"), rel_tol, max_vcycles,
                                             done, fin, st), self.b)
+        return {"status": s, "vcycles": list(done), "energy": list(fin), "image_status": list(st)}
+
+    def solve_target(self, u, f, target_energy, max_vcycles: int = 1000):
+        done = (C.c_int32 * self.n)()
+        fin = (C.c_double * self.n)()
+        st = (C.c_int32 * self.n)()
+        tg = (C.c_double * self.n)(*[float(x) for x in target_energy])
+        s = _bcheck(lib.mg_curv_batch_solve_target(self.b, self._ptr(u, "u"), self._ptr(f, "f"), tg, max_vcycles,
+                                                   done, fin, st), self.b)
         return {"status": s, "vcycles": list(done), "energy": list(fin), "image_status": list(st)}
 
     def tune(self, u, f, repeats: int = 2):

@@ -1,0 +1,60 @@
+"""GPU tests of the learned warm start with the committed trained weights.
+
+The gain test runs the plain batched solve from u0 = f (relative energy change 1e-6) and the
+warm-started one (u0 = f + g(f), then V-cycles until the plain final energy (1 + 1e-6) is
+reached) on images the network never saw, and checks that the warm start reaches the plain
+energy in fewer V-cycles and less wall time, CNN included.  The fallback test forces an
+unreachable target and checks that the refinement reports it."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ws():
+    from paper_2204_07921_amd import warmstart
+    if not os.path.exists(warmstart.DEFAULT_WEIGHTS):
+        pytest.skip("trained weights are not in the tree")
+    return warmstart
+
+
+def test_weights_load_and_match_layout(ws):
+    from paper_2204_07921_amd import mgcurv
+    params, meta = ws.load()
+    assert params.size == 37601 and np.all(np.isfinite(params))
+    net = mgcurv.WarmStartCNN(64 * 64, params)
+    assert np.array_equal(net.get_params(), params)
+
+
+def test_warm_start_gain(ws):
+    from paper_2204_07921_amd import mgcurv
+    params, _ = ws.load()
+    print("\n[case] warm-start gain, 6 images of 512x512", flush=True)
+    f = ws.make_inputs(6, 512, seed0=200000)
+    net = mgcurv.WarmStartCNN(4 * 512 * 512, params)
+    ws.forward_chunked(net, f)   # warm-up
+    r = ws.evaluate(net, f, max_vcycles=600)
+    print(r)
+    assert r["warm"]["reached_plain_energy"] >= 5
+    assert r["warm"]["vcycles_mean"] < r["plain"]["vcycles_mean"]
+    assert r["warm"]["seconds"] < r["plain"]["seconds"]
+    assert r["final_energy_gap_rel_max"] <= 1e-6
+
+
+def test_unreachable_target_reports_not_converged(ws):
+    from paper_2204_07921_amd import mgcurv
+    params, _ = ws.load()
+    f = ws.make_inputs(2, 128, seed0=300000)
+    net = mgcurv.WarmStartCNN(2 * 128 * 128, params)
+    u0 = ws.forward_chunked(net, f)
+    _, res = ws.solve_batch(f, u0=u0, targets=[0.0, 0.0], max_vcycles=3, tune=False)
+    assert res["status"] == 1 and res["image_status"] == [1, 1] and res["vcycles"] == [3, 3]
+    s = mgcurv.Solver(128, 128, dtype=torch.float32)
+    r1 = s.solve_target(u0[0].contiguous(), f[0].contiguous(), 0.0, max_vcycles=2)
+    assert r1["status"] == 1 and r1["vcycles"] == 2
+    r2 = s.solve_target(u0[0].contiguous(), f[0].contiguous(), 1e30, max_vcycles=5)
+    assert r2["status"] == 0 and r2["vcycles"] == 0
