@@ -53,6 +53,8 @@ __device__ __forceinline__ int find_slot(const int* __restrict__ cum, int n, int
 
 // Pixel level, four colours, two-phase (uin -> uout).  Inactive images are
 // skipped in every pass, so after the four passes their data is still in uin = u.
+// Interior cells (cum_in) take one thread each (constant-slope form); the outer
+// ring of cells of every image (cum_ring) takes a 16-lane group per cell.
 __global__ __launch_bounds__(256) void batch_pixels_kernel(const float* __restrict__ uin, float* __restrict__ uout,
                                                            const float* __restrict__ f, const BatchImg* __restrict__ imgs,
                                                            const int* __restrict__ order, const int* __restrict__ cum,
@@ -64,13 +66,38 @@ __global__ __launch_bounds__(256) void batch_pixels_kernel(const float* __restri
         const int img = order[k];
         if (!active[img]) continue;
         const BatchImg im = imgs[img];
-        const int cells_c = (im.W + 1) / 2;
+        const int ic = (im.W + 1) / 2 - 2;
         const int cell = t - cum[k];
-        const int cr = cell / cells_c, cc = cell - cr * cells_c;
+        const int cr = 1 + cell / ic, cc = 1 + cell % ic;
         if (im.kind == 0)
-            solve_cell<float, 0, 2>(uin + im.off, uout + im.off, f + im.off, im.H, im.W, colour, cr, cc, im.alpha, M, G);
+            solve_cell<float, 0, 2, 1>(uin + im.off, uout + im.off, f + im.off, im.H, im.W, colour, cr, cc, im.alpha, M, G);
         else
-            solve_cell<float, 1, 2>(uin + im.off, uout + im.off, f + im.off, im.H, im.W, colour, cr, cc, im.alpha, M, G);
+            solve_cell<float, 1, 2, 1>(uin + im.off, uout + im.off, f + im.off, im.H, im.W, colour, cr, cc, im.alpha, M, G);
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_ring_cells_kernel(const float* __restrict__ uin, float* __restrict__ uout,
+                                                               const float* __restrict__ f,
+                                                               const BatchImg* __restrict__ imgs,
+                                                               const int* __restrict__ order, const int* __restrict__ cum,
+                                                               int n, int total, const int* __restrict__ active,
+                                                               int colour, int M, int G)
+{
+    const int ngroups = gridDim.x * (blockDim.x / 16);
+    const int lane = threadIdx.x & 15;
+    for (int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; t < total; t += ngroups) {
+        const int k = find_slot(cum, n, t);
+        const int img = order[k];
+        if (!active[img]) continue;   // uniform within the group
+        const BatchImg im = imgs[img];
+        int cr, cc;
+        ring_cell(t - cum[k], (im.H + 1) / 2, (im.W + 1) / 2, cr, cc);
+        if (im.kind == 0)
+            solve_ring_cell<float, 0, 2>(uin + im.off, uout + im.off, f + im.off, im.H, im.W, colour, cr, cc, lane,
+                                         im.alpha, M, G);
+        else
+            solve_ring_cell<float, 1, 2>(uin + im.off, uout + im.off, f + im.off, im.H, im.W, colour, cr, cc, lane,
+                                         im.alpha, M, G);
     }
 }
 
@@ -306,9 +333,11 @@ struct mg_curv_batch {
     int* d_order = nullptr;
     int* d_active = nullptr;
     float* pingpong = nullptr;
-    // pixel level: cumulative cell counts in kind order
+    // pixel level: cumulative interior-cell and ring-cell counts in kind order
     int* d_cells_cum = nullptr;
     int cells_total = 0;
+    int* d_ring_cum = nullptr;
+    int ring_total = 0;
     // block levels: [level][colour] cumulative same-colour block counts
     std::vector<int*> d_blk_cum;              // index (level - 2) * 4 + colour
     std::vector<int> blk_total;
@@ -450,8 +479,13 @@ mg_status batch_level(mg_curv_batch* b, hipStream_t s, float* u, const float* f,
         const float* cur = u;
         float* nxt = b->pingpong;
         for (int colour = 0; colour < 4; ++colour) {
-            hipLaunchKernelGGL(mgc::batch_pixels_kernel, dim3(b->grid[0]), dim3(256), 0, s, cur, nxt, f, b->d_imgs,
-                               b->d_order, b->d_cells_cum, b->n, b->cells_total, b->d_active, colour, b->M, b->G);
+            if (b->ring_total > 0)
+                hipLaunchKernelGGL(mgc::batch_ring_cells_kernel, dim3(std::min((b->ring_total * 16 + 255) / 256, 4096)),
+                                   dim3(256), 0, s, cur, nxt, f, b->d_imgs, b->d_order, b->d_ring_cum, b->n,
+                                   b->ring_total, b->d_active, colour, b->M, b->G);
+            if (b->cells_total > 0)
+                hipLaunchKernelGGL(mgc::batch_pixels_kernel, dim3(b->grid[0]), dim3(256), 0, s, cur, nxt, f, b->d_imgs,
+                                   b->d_order, b->d_cells_cum, b->n, b->cells_total, b->d_active, colour, b->M, b->G);
             e = hipGetLastError();
             if (e != hipSuccess) return bhip(b, e, "batched pixel sweep");
             float* t = (float*)cur;
@@ -567,13 +601,17 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
     ok = ok && upload(b, &b->d_imgs, b->h_imgs) && upload(b, &b->d_order, b->h_order) && upload(b, &b->d_active, b->h_active);
     ok = ok && dalloc(b, &b->pingpong, (size_t)b->total_elems);
     // pixel level
-    std::vector<int> cum(1, 0);
+    std::vector<int> cum(1, 0), rcum(1, 0);
     for (int k = 0; k < n; ++k) {
         const BatchImg& im = b->h_imgs[b->h_order[k]];
-        cum.push_back(cum.back() + ((im.H + 1) / 2) * ((im.W + 1) / 2));
+        const int cr = (im.H + 1) / 2, cc = (im.W + 1) / 2;
+        const int inner = (cr > 2 && cc > 2) ? (cr - 2) * (cc - 2) : 0;
+        cum.push_back(cum.back() + inner);
+        rcum.push_back(rcum.back() + mgc::ring_cell_count(cr, cc));
     }
     b->cells_total = cum.back();
-    ok = ok && upload(b, &b->d_cells_cum, cum);
+    b->ring_total = rcum.back();
+    ok = ok && upload(b, &b->d_cells_cum, cum) && upload(b, &b->d_ring_cum, rcum);
     // block levels
     size_t max_part = 1, max_pend = 1;
     for (int level = 2; level <= b->Jmax; ++level) {

@@ -22,7 +22,7 @@ namespace mgc {
 // pixel of the active colour and copies the cell's other pixels.
 // ---------------------------------------------------------------------------
 // Interior cells (every cell but the outer ring of cells): all their pixels
-// lie inside the image and off its border.
+// lie inside the image and off its border (constant-slope form).
 template <typename T, int KIND, int NC>
 __global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                            const T* __restrict__ f, int H, int W, int colour,
@@ -35,26 +35,18 @@ __global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__
     solve_cell<T, KIND, NC, 1>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
 }
 
-// The outer ring of cells (first and last cell row and column).
+// The outer ring of cells (first and last cell row and column), 16 lanes per
+// cell.  Launched on a second stream so that it overlaps the interior sweep.
 template <typename T, int KIND, int NC>
 __global__ __launch_bounds__(256) void sweep_pixels_border_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                                   const T* __restrict__ f, int H, int W, int colour,
                                                                   int cells_r, int cells_c, double alpha, int M, int G)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int lane = threadIdx.x & 15;
     int cr, cc;
-    if (cells_r <= 2 || cells_c <= 2) {   // every cell is on the ring
-        if (k >= cells_r * cells_c) return;
-        cr = k / cells_c;
-        cc = k % cells_c;
-    } else {
-        if (k < cells_c) { cr = 0; cc = k; }
-        else if ((k -= cells_c) < cells_c) { cr = cells_r - 1; cc = k; }
-        else if ((k -= cells_c) < cells_r - 2) { cr = 1 + k; cc = 0; }
-        else if ((k -= cells_r - 2) < cells_r - 2) { cr = 1 + k; cc = cells_c - 1; }
-        else return;
-    }
-    solve_cell<T, KIND, NC, 0>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
+    if (!ring_cell(k, cells_r, cells_c, cr, cc)) return;   // whole groups exit together
+    solve_ring_cell<T, KIND, NC>(uin, uout, f, H, W, colour, cr, cc, lane, alpha, M, G);
 }
 
 template <typename T, int KIND, int GROUP, int RPL, bool LAZY>
@@ -173,13 +165,27 @@ static hipError_t launch_pixels_nc(const LaunchCtx& L, const void* uin, void* uo
 {
     const int cells_r = (L.H + NC - 1) / NC, cells_c = (L.W + NC - 1) / NC;
     const int n_in = (cells_r > 2 && cells_c > 2) ? (cells_r - 2) * (cells_c - 2) : 0;
-    const int n_border = cells_r * cells_c - n_in;
+    const int n_border = ring_cell_count(cells_r, cells_c);
+    // fork: the border ring runs on the side stream after everything enqueued so far
+    hipStream_t bs = L.side ? L.side : L.stream;
+    hipError_t e;
+    if (L.side) {
+        if ((e = hipEventRecord(L.ev_fork, L.stream)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(L.side, L.ev_fork, 0)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((sweep_pixels_border_kernel<T, KIND, NC>), dim3((n_border * 16 + 255) / 256), dim3(256), 0, bs,
+                       (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n_in > 0)
         hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, NC>), dim3((n_in + 255) / 256), dim3(256), 0, L.stream,
                            (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
-    hipLaunchKernelGGL((sweep_pixels_border_kernel<T, KIND, NC>), dim3((n_border + 255) / 256), dim3(256), 0, L.stream,
-                       (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // join: later work on the main stream waits for the border ring
+    if (L.side) {
+        if ((e = hipEventRecord(L.ev_join, L.side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(L.stream, L.ev_join, 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T, int KIND>

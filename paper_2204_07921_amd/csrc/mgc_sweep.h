@@ -228,6 +228,65 @@ __device__ __forceinline__ void solve_cell(const T* __restrict__ uin, T* __restr
     }
 }
 
+// Pixel level, a cell of the outer ring of cells (its pixel may sit on the
+// image border, where clamped taps can alias the pixel itself): a 16-lane
+// group per cell, lane t < 9 owning the ring record of neighbour
+// (t / 3 - 1, t % 3 - 1), so each evaluation is one record plus a butterfly.
+// Lanes t < NC * NC then write pixel t of the cell into uout.
+__device__ __forceinline__ bool ring_cell(int k, int cells_r, int cells_c, int& cr, int& cc)
+{
+    if (cells_r <= 2 || cells_c <= 2) {   // every cell is on the ring
+        if (k >= cells_r * cells_c) return false;
+        cr = k / cells_c;
+        cc = k % cells_c;
+        return true;
+    }
+    if (k < cells_c) { cr = 0; cc = k; return true; }
+    if ((k -= cells_c) < cells_c) { cr = cells_r - 1; cc = k; return true; }
+    if ((k -= cells_c) < cells_r - 2) { cr = 1 + k; cc = 0; return true; }
+    if ((k -= cells_r - 2) < cells_r - 2) { cr = 1 + k; cc = cells_c - 1; return true; }
+    return false;
+}
+
+__host__ __device__ __forceinline__ int ring_cell_count(int cells_r, int cells_c)
+{
+    return (cells_r <= 2 || cells_c <= 2) ? cells_r * cells_c : 2 * cells_c + 2 * (cells_r - 2);
+}
+
+template <typename T, int KIND, int NC>
+__device__ __forceinline__ void solve_ring_cell(const T* __restrict__ uin, T* __restrict__ uout,
+                                                const T* __restrict__ f, int H, int W, int colour, int cr, int cc,
+                                                int lane, double alpha, int M, int G)
+{
+    const int i = NC * cr + colour / NC;
+    const int j = NC * cc + colour % NC;
+    double cval = 0.0;
+    if (i < H && j < W) {   // uniform within the group
+        Ring rg;
+        if (lane < 9)
+            make_ring(uin, H, W, i + lane / 3 - 1, j + lane % 3 - 1, i, i + 1, j, j + 1, rg);
+        else
+            zero_ring(rg);
+        const double fs = (double)f[(size_t)i * W + j] - (double)uin[(size_t)i * W + j];
+        auto Kpart = [&](const auto& cs, auto& out) {
+            constexpr int N = sizeof(out) / sizeof(double);
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k] = abs_kappa<KIND>(rg, cs[k]);
+        };
+        auto Dpart = [&](double c) { return dabs_kappa<KIND>(rg, c); };
+        cval = local_solve(Kpart, Dpart, WaveSum<16>(), fs, alpha, M, G);
+    }
+    if (lane < NC * NC) {
+        const int ii = NC * cr + lane / NC, jj = NC * cc + lane % NC;
+        if (ii < H && jj < W) {
+            const size_t idx = (size_t)ii * W + jj;
+            T v = uin[idx];
+            if (ii == i && jj == j) v = (T)((double)v + cval);
+            uout[idx] = v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Ring candidates of block rows [r0, r1) x cols [c0, c1): the pixels of the box
 // [r0 - 1, r1] x [c0 - 1, c1] at distance <= 1 from the block's boundary.
