@@ -34,13 +34,21 @@ ALPHA = 20.0
 SIGMA = 0.1
 SEED = 0
 
-# Algorithmic FP64 operation counts of one ring-pixel evaluation (FMA = 2,
-# rsqrt / reciprocal = 1), counted from the formulas of the local solver.
-FLOPS_VALUE = {0: 30, 1: 26}        # |kappa| at a shift c (mean, Gaussian)
-FLOPS_DERIV = {0: 60, 1: 44}        # d|kappa|/dc at a shift c
-# evaluations per block solve with M = 16 samples, G = 32 bisection steps:
-# K(0), K(f*), 16 further samples, K at the bisection point; 32 derivatives.
+# FP64 operations (FMA = 2, rsqrt / reciprocal / abs-multiply = 1) that the pixel-level
+# kernel evaluates per solved interior pixel, counted from its formulas: the centre and the four
+# diagonal ring pixels have a constant q, so their curvature is linear (mean) or quadratic
+# (Gaussian) in c; the four edge neighbours use the full rational form with constant slopes.
+#   mean:     |K| evaluation 5 x 4 + 4 x 23 = 112,  derivative 5 x 5 + 4 x 38 = 177
+#   Gaussian: |K| evaluation 30 + 4 x 14 = 86,       derivative 45 + 4 x 22 = 133
+# Evaluations per pixel with M = 16 samples and G = 32 bisection steps: K(0), K(f*), 16 further
+# samples and K at the bisection point (19), and 32 derivatives.
+FLOPS_VALUE = {0: 112, 1: 86}
+FLOPS_DERIV = {0: 177, 1: 133}
 N_VALUE, N_DERIV = 19, 32
+# For reference, the general affine-record form of the same evaluations (all nine ring pixels
+# with runtime slopes) costs 9 x 30 and 9 x 60 (mean), 9 x 26 and 9 x 44 (Gaussian).
+FLOPS_VALUE_GENERAL = {0: 270, 1: 234}
+FLOPS_DERIV_GENERAL = {0: 540, 1: 396}
 FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
 
 
@@ -226,8 +234,8 @@ def main():
     launches = reps * 4
     avg_ms = ev0.elapsed_time(ev1) / launches
     pixels_per_launch = (H // 2) * (W // 2)
-    ring = 9
-    flops_launch = pixels_per_launch * ring * (N_VALUE * FLOPS_VALUE[args.kind] + N_DERIV * FLOPS_DERIV[args.kind])
+    flops_launch = pixels_per_launch * (N_VALUE * FLOPS_VALUE[args.kind] + N_DERIV * FLOPS_DERIV[args.kind])
+    flops_general = pixels_per_launch * (N_VALUE * FLOPS_VALUE_GENERAL[args.kind] + N_DERIV * FLOPS_DERIV_GENERAL[args.kind])
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
 
     # per-level times (one V-cycle's share), for the report
@@ -280,7 +288,10 @@ def main():
                                                  f"mgc::sweep_pixels_kernel<float, {args.kind}"),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "sweep_pixels_kernel (b = 1)", "avg_launch_ms": round(avg_ms, 5),
-                     "flops_per_launch": flops_launch},
+                     "flops_per_launch": flops_launch,
+                     "general_form_equivalent_tflops": round(flops_general / (avg_ms * 1e-3) / 1e12, 3),
+                     "note": "one launch = one colour of the pixel level (outer ring of cells on 16-lane "
+                             "groups, interior cells one thread each), timed with HIP events on the library stream"},
         "level_ms": level_ms,
         "energy_last": energies[-1],
         "time_to_tol": solves,

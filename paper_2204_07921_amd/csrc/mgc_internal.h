@@ -7,8 +7,6 @@ namespace mgc {
 
 struct LaunchCtx {
     hipStream_t stream;
-    hipStream_t side;        // optional second stream (pixel-level border ring); null: use `stream`
-    hipEvent_t ev_fork, ev_join;
     int H, W;
     double alpha;
     int kind;   // 0 mean, 1 Gaussian

@@ -21,32 +21,30 @@ namespace mgc {
 // (2x2 cells for four colours, 3x3 for nine); the thread solves the cell's
 // pixel of the active colour and copies the cell's other pixels.
 // ---------------------------------------------------------------------------
-// Interior cells (every cell but the outer ring of cells): all their pixels
-// lie inside the image and off its border (constant-slope form).
+// One launch per colour.  The first `ring_blocks` workgroups take the outer
+// ring of cells (first and last cell row and column) with a 16-lane group per
+// cell (general form: the pixel may sit on the image border); they come first
+// so their longer per-cell solves overlap the rest of the grid, which takes the
+// interior cells one thread each (constant-slope form).
 template <typename T, int KIND, int NC>
 __global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                            const T* __restrict__ f, int H, int W, int colour,
-                                                           int cells_r, int cells_c, double alpha, int M, int G)
+                                                           int cells_r, int cells_c, int ring_blocks, double alpha,
+                                                           int M, int G)
 {
+    if ((int)blockIdx.x < ring_blocks) {
+        const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+        const int lane = threadIdx.x & 15;
+        int cr, cc;
+        if (!ring_cell(k, cells_r, cells_c, cr, cc)) return;   // whole groups exit together
+        solve_ring_cell<T, KIND, NC>(uin, uout, f, H, W, colour, cr, cc, lane, alpha, M, G);
+        return;
+    }
     const int ir = cells_r - 2, ic = cells_c - 2;
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= ir * ic) return;
+    const int cell = (blockIdx.x - ring_blocks) * blockDim.x + threadIdx.x;
+    if (ir <= 0 || ic <= 0 || cell >= ir * ic) return;
     const int cr = 1 + cell / ic, cc = 1 + cell % ic;
     solve_cell<T, KIND, NC, 1>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
-}
-
-// The outer ring of cells (first and last cell row and column), 16 lanes per
-// cell.  Launched on a second stream so that it overlaps the interior sweep.
-template <typename T, int KIND, int NC>
-__global__ __launch_bounds__(256) void sweep_pixels_border_kernel(const T* __restrict__ uin, T* __restrict__ uout,
-                                                                  const T* __restrict__ f, int H, int W, int colour,
-                                                                  int cells_r, int cells_c, double alpha, int M, int G)
-{
-    const int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    const int lane = threadIdx.x & 15;
-    int cr, cc;
-    if (!ring_cell(k, cells_r, cells_c, cr, cc)) return;   // whole groups exit together
-    solve_ring_cell<T, KIND, NC>(uin, uout, f, H, W, colour, cr, cc, lane, alpha, M, G);
 }
 
 template <typename T, int KIND, int GROUP, int RPL, bool LAZY>
@@ -165,27 +163,10 @@ static hipError_t launch_pixels_nc(const LaunchCtx& L, const void* uin, void* uo
 {
     const int cells_r = (L.H + NC - 1) / NC, cells_c = (L.W + NC - 1) / NC;
     const int n_in = (cells_r > 2 && cells_c > 2) ? (cells_r - 2) * (cells_c - 2) : 0;
-    const int n_border = ring_cell_count(cells_r, cells_c);
-    // fork: the border ring runs on the side stream after everything enqueued so far
-    hipStream_t bs = L.side ? L.side : L.stream;
-    hipError_t e;
-    if (L.side) {
-        if ((e = hipEventRecord(L.ev_fork, L.stream)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(L.side, L.ev_fork, 0)) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((sweep_pixels_border_kernel<T, KIND, NC>), dim3((n_border * 16 + 255) / 256), dim3(256), 0, bs,
-                       (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (n_in > 0)
-        hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, NC>), dim3((n_in + 255) / 256), dim3(256), 0, L.stream,
-                           (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, L.alpha, L.M, L.G);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // join: later work on the main stream waits for the border ring
-    if (L.side) {
-        if ((e = hipEventRecord(L.ev_join, L.side)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(L.stream, L.ev_join, 0)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int rb = (ring_cell_count(cells_r, cells_c) * 16 + 255) / 256;
+    hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, NC>), dim3(rb + (n_in + 255) / 256), dim3(256), 0, L.stream,
+                       (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, rb, L.alpha, L.M, L.G);
+    return hipGetLastError();
 }
 
 template <typename T, int KIND>

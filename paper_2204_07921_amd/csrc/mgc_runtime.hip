@@ -18,8 +18,6 @@ struct mg_curv_ctx {
     int J;
     int device;
     hipStream_t stream;
-    hipStream_t side;      // second stream for the pixel level's border ring (default priority)
-    hipEvent_t ev_fork, ev_join;
     void* pingpong;        // H x W state-dtype image for the two-phase pixel level
     double* partials;      // energy partial sums
     mgc::CoarseScratch coarse;  // block sums and pending corrections of the coarse levels
@@ -64,9 +62,6 @@ mgc::LaunchCtx launch_ctx(const mg_curv_ctx* c)
 {
     mgc::LaunchCtx L;
     L.stream = c->stream;
-    L.side = c->side;
-    L.ev_fork = c->ev_fork;
-    L.ev_join = c->ev_join;
     L.H = c->P.height;
     L.W = c->P.width;
     L.alpha = c->P.alpha;
@@ -212,9 +207,6 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->P = p;
     c->J = p.levels > 0 ? p.levels : auto_levels(p.height, p.width);
     c->stream = (hipStream_t)hip_stream;
-    c->side = nullptr;
-    c->ev_fork = nullptr;
-    c->ev_join = nullptr;
     c->pingpong = nullptr;
     c->partials = nullptr;
     c->energy_dev = nullptr;
@@ -236,10 +228,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
         hipMalloc((void**)&c->coarse.partials, sizeof(double) * n_part) != hipSuccess ||
         hipMalloc((void**)&c->coarse.cpend, sizeof(double) * n_pend) != hipSuccess ||
         hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         mg_curv_destroy(c);
         (void)hipGetLastError();
         return fail(nullptr, MG_E_NOMEM, "device allocation of %zu bytes failed", nb);
@@ -347,9 +336,6 @@ void mg_curv_destroy(mg_curv_ctx* ctx)
     if (ctx->coarse.cpend) (void)hipFree(ctx->coarse.cpend);
     if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
     if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
-    if (ctx->side) { (void)hipStreamSynchronize(ctx->side); (void)hipStreamDestroy(ctx->side); }
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 
