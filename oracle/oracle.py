@@ -10,6 +10,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mgc_oracle.c")
+_SRC_FBS = os.path.join(_HERE, "fbs_oracle.c")
+SOURCES = (_SRC, _SRC_FBS)
 
 
 def lib_path() -> str:
@@ -20,12 +22,16 @@ def lib_path() -> str:
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (-O2, FP64, OpenMP; no fast-math)."""
     out = lib_path()
-    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+    if force or _stale(out):
         tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+                               "-fno-fast-math", "-ffp-contract=off", *SOURCES, "-o", tmp, "-lm"])
         os.replace(tmp, out)
     return out
+
+
+def _stale(out: str) -> bool:
+    return not os.path.exists(out) or any(os.path.getmtime(out) < os.path.getmtime(s) for s in SOURCES)
 
 
 class OracleParams(C.Structure):
@@ -54,8 +60,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.environ.get("MGC_ORACLE_LIB") and (
-                not os.path.exists(lib_path()) or os.path.getmtime(lib_path()) < os.path.getmtime(_SRC)):
+        if not os.environ.get("MGC_ORACLE_LIB") and _stale(lib_path()):
             build(force=True)
         L = C.CDLL(lib_path())
         P = C.POINTER(OracleParams)
@@ -86,6 +91,28 @@ def _load():
         L.orc_solve.argtypes = [P, _DP, _DP, C.c_double, C.c_int, C.c_void_p]
         L.orc_num_colours.restype = C.c_int
         L.orc_num_colours.argtypes = [P, C.c_int]
+        FP = C.POINTER(FbsParams)
+        L.fbs_plane.restype = None
+        L.fbs_plane.argtypes = [FP, _DP, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.fbs_estimate.restype = C.c_double
+        L.fbs_estimate.argtypes = [FP, _DP, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.fbs_block_step.restype = C.c_double
+        L.fbs_block_step.argtypes = [FP, _DP, _DP, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+        L.fbs_sweep.restype = C.c_int
+        L.fbs_sweep.argtypes = [FP, _DP, _DP, C.c_int, C.c_int, C.c_void_p]
+        L.fbs_level.restype = None
+        L.fbs_level.argtypes = [FP, _DP, _DP, C.c_int]
+        L.fbs_vcycle.restype = None
+        L.fbs_vcycle.argtypes = [FP, _DP, _DP]
+        L.fbs_solve.restype = C.c_int
+        L.fbs_solve.argtypes = [FP, _DP, _DP, C.c_double, C.c_int, C.c_int, C.c_void_p]
+        for name in ("fbs_block_side", "fbs_rings", "fbs_planes"):
+            getattr(L, name).restype = C.c_int
+            getattr(L, name).argtypes = [C.c_int]
+        for name in ("fbs_grid_rows", "fbs_grid_cols"):
+            getattr(L, name).restype = C.c_int
+            getattr(L, name).argtypes = [FP, C.c_int]
         _lib = L
     return _lib
 
@@ -191,6 +218,83 @@ class Oracle:
         assert u.dtype == np.float64 and u.flags.c_contiguous
         trace = np.zeros(max_vcycles + 1)
         n = self.L.orc_solve(C.byref(self.p), u, _f64(f), rel_tol, max_vcycles, trace.ctypes.data)
+        return n, trace[: n + 1].copy()
+
+    def energy(self, u, f) -> float:
+        return energy(self.p.kind, u, f, self.p.alpha)
+
+
+class FbsParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
+                ("kind", C.c_int32), ("levels", C.c_int32), ("steps", C.c_int32), ("cycle", C.c_int32),
+                ("round_f32", C.c_int32), ("threads", C.c_int32)]
+
+
+class FbsOracle:
+    """FP64 reference of the paper's FBS local step (Algorithm 2, Propositions 1-2) on
+    patches of side 2^j - 1 (Section 2.2)."""
+
+    def __init__(self, height: int, width: int, alpha: float, kind: int = 0, levels: int = 3,
+                 steps: int = 1, cycle: int = 0, round_f32: bool = False, threads: int = 1):
+        self.p = FbsParams(height, width, float(alpha), kind, levels, steps, cycle,
+                           int(bool(round_f32)), threads)
+        self.L = _load()
+
+    @property
+    def levels(self) -> int:
+        return self.p.levels
+
+    def block_side(self, level: int) -> int:
+        return self.L.fbs_block_side(level)
+
+    def rings(self, level: int) -> int:
+        return self.L.fbs_rings(level)
+
+    def grid(self, level: int) -> tuple[int, int]:
+        return (self.L.fbs_grid_rows(C.byref(self.p), level), self.L.fbs_grid_cols(C.byref(self.p), level))
+
+    def block_bounds(self, level: int, p: int, q: int) -> tuple[int, int, int, int]:
+        b = self.block_side(level)
+        return (p * b, min((p + 1) * b, self.p.height), q * b, min((q + 1) * b, self.p.width))
+
+    @staticmethod
+    def colour_of(p: int, q: int) -> int:
+        return 2 * (p % 2) + (q % 2)
+
+    def plane(self, u, level: int, p: int, q: int, r: int, k: int, c: float = 0.0) -> tuple[float, float]:
+        d, ds2 = C.c_double(), C.c_double()
+        self.L.fbs_plane(C.byref(self.p), _f64(u), level, p, q, c, r, k, C.byref(d), C.byref(ds2))
+        return d.value, ds2.value
+
+    def estimate(self, u, level: int, p: int, q: int, c: float = 0.0) -> float:
+        return self.L.fbs_estimate(C.byref(self.p), _f64(u), level, p, q, c)
+
+    def block_step(self, u, f, level: int, p: int, q: int):
+        """(c, trace[steps, 3] of (c_t, c_{t+1/2}, eta_t), s, f*)."""
+        tr = np.zeros((self.p.steps, 3))
+        info = np.zeros(2)
+        c = self.L.fbs_block_step(C.byref(self.p), _f64(u), _f64(f), level, p, q, tr.ctypes.data, info.ctypes.data)
+        return c, tr, info[0], info[1]
+
+    def sweep(self, u: np.ndarray, f, level: int, colour: int, want_c: bool = False):
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        cb = np.zeros(self.grid(level)) if want_c else None
+        self.L.fbs_sweep(C.byref(self.p), u, _f64(f), level, colour, cb.ctypes.data if cb is not None else None)
+        return cb
+
+    def level(self, u: np.ndarray, f, level: int) -> None:
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        self.L.fbs_level(C.byref(self.p), u, _f64(f), level)
+
+    def vcycle(self, u: np.ndarray, f) -> None:
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        self.L.fbs_vcycle(C.byref(self.p), u, _f64(f))
+
+    def solve(self, u: np.ndarray, f, tol: float = 1e-6, max_vcycles: int = 1000, stop: int = 0):
+        """In-place solve; stop 0 = relative energy change, 1 = relErr(u).  Returns (done, energies)."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        trace = np.zeros(max_vcycles + 1)
+        n = self.L.fbs_solve(C.byref(self.p), u, _f64(f), tol, max_vcycles, stop, trace.ctypes.data)
         return n, trace[: n + 1].copy()
 
     def energy(self, u, f) -> float:

@@ -11,6 +11,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "mgc_oracle.c")
+SRC_FBS = os.path.join(ROOT, "oracle", "fbs_oracle.c")
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+PINS_FBS = os.path.join(ROOT, "tests", "test_fbs_oracle_pins.py")
 
 # (name, original text, mutated text); every original must occur in the source.
 MUTANTS = [
@@ -41,30 +44,57 @@ MUTANTS = [
 ]
 
 
-def _build_mutant(tmp, name, old, new):
-    src = open(SRC).read()
+# Mistakes planted in the FBS oracle (the paper's own local step), caught by its pins.
+MUTANTS_FBS = [
+    ("fbs_diag_third_vertex", "{{-1, 1}, {1, -1}},   /* NW-SE with NE, SW */", "{{-1, 0}, {1, 0}},   /* NW-SE with NE, SW */"),
+    ("fbs_normal_not_oriented", "if (n[2] < 0.0) {", "if (n[2] < -1e300) {"),
+    ("fbs_distance_not_normalised", "/ len;\n    *ds2", "/ n[2];\n    *ds2"),
+    ("fbs_ds2_factor", "*ds2 = 0.25 * (", "*ds2 = 0.5 * ("),
+    ("fbs_ds2_flat", "*ds2 = 0.25 * (e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);",
+     "*ds2 = 0.25 * (e1[0] * e1[0] + e1[1] * e1[1]);"),
+    ("fbs_gc_larger_magnitude", "return fabs(kmin) <= fabs(kmax) ? dmin : dmax;", "return fabs(kmin) >= fabs(kmax) ? dmin : dmax;"),
+    ("fbs_mc_mean_over_one_ring", "return acc / (double)(8 * R);", "return acc / 8.0;"),
+    ("fbs_rings_short", "for (int r = 1; r <= R; ++r)\n            for (int k = 0; k < 8; ++k) {\n                double d, ds2;\n                fbs_plane(P, u, level, p, q, c, r, k, &d, &ds2);\n                acc",
+     "for (int r = 1; r < R || r == 1; ++r)\n            for (int k = 0; k < 8; ++k) {\n                double d, ds2;\n                fbs_plane(P, u, level, p, q, c, r, k, &d, &ds2);\n                acc"),
+    ("fbs_eta_schedule", "eta = 1.0 / sqrt(1.0 + (double)t);", "eta = 1.0 / sqrt(2.0 + (double)t);"),
+    ("fbs_one_proximal_term", "double next = (c + half + w * fs) / (2.0 + w);", "double next = (half + w * fs) / (1.0 + w);"),
+    ("fbs_half_not_shifted", "double half = c + fbs_estimate(", "double half = fbs_estimate("),
+    ("fbs_estimate_unshifted_state", "double half = c + fbs_estimate(P, u, level, p, q, c);", "double half = c + fbs_estimate(P, u, level, p, q, 0.0);"),
+    ("fbs_sum_not_mean", "const double fs = acc / s;", "const double fs = acc;"),
+    ("fbs_centre_offset", "B.oi = B.r0 + (b - 1) / 2;", "B.oi = B.r0 + (b + 1) / 2;"),
+    ("fbs_colour_map", "int fbs_colour(int p, int q) { return 2 * (p % 2) + (q % 2); }",
+     "int fbs_colour(int p, int q) { return 2 * (q % 2) + (p % 2); }"),
+    ("fbs_wrap_not_clamp", "int ci = clampi(i, 0, P->height - 1), cj", "int ci = (i + P->height) % P->height, cj"),
+    ("fbs_block_side", "int fbs_block_side(int level) { return (1 << level) - 1; }",
+     "int fbs_block_side(int level) { return 1 << (level - 1); }"),
+]
+
+
+def _build_mutant(tmp, name, old, new, src_path=SRC):
+    src = open(src_path).read()
     assert old in src, name
     path_c = os.path.join(tmp, name + ".c")
     with open(path_c, "w") as fh:
         fh.write(src.replace(old, new, 1))
+    others = [p for p in (SRC, SRC_FBS) if p != src_path]
     path_so = os.path.join(tmp, name + ".so")
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-                           path_c, "-o", path_so, "-lm"])
+                           path_c, *others, "-o", path_so, "-lm"])
     return path_so
 
 
-def _run_pins(so):
+def _run_pins(so, pins=PINS):
     env = dict(os.environ, MGC_ORACLE_LIB=so)
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pins],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     return r.returncode
 
 
 def test_every_planted_mistake_is_caught():
     with tempfile.TemporaryDirectory() as tmp:
-        sos = [(m[0], _build_mutant(tmp, *m)) for m in MUTANTS]
+        jobs = [(m[0], _build_mutant(tmp, *m), PINS) for m in MUTANTS]
+        jobs += [(m[0], _build_mutant(tmp, *m, src_path=SRC_FBS), PINS_FBS) for m in MUTANTS_FBS]
         with ThreadPoolExecutor(max_workers=6) as ex:
-            codes = list(ex.map(lambda x: _run_pins(x[1]), sos))
-    survivors = [name for (name, _), code in zip(sos, codes) if code == 0]
+            codes = list(ex.map(lambda x: _run_pins(x[1], x[2]), jobs))
+    survivors = [name for (name, _, _), code in zip(jobs, codes) if code == 0]
     assert not survivors, f"pins did not catch: {survivors}"
