@@ -250,6 +250,84 @@ mg_status mg_cnn_activation(mg_cnn *c, int32_t layer, void *host_out, int64_t co
 void mg_cnn_destroy(mg_cnn *c);
 const char *mg_cnn_last_error(const mg_cnn *c);
 
+/* ------------------------------------------------------------------------
+ * The paper's own local step (Section 2.1-2.2, Algorithm 2, Propositions 1-2).
+ * Patches of side b_j = 2^j - 1 on level j = 1..J (Section 2.2: m_j =
+ * ceil(H / b_j) rows and n_j = ceil(W / b_j) columns of patches anchored at the
+ * top-left pixel, clipped at the right and bottom edges; positions outside the
+ * image take the value of the nearest image pixel), the four-colour order of
+ * Section 2.3, and per patch `steps` forward-backward splitting updates:
+ *     c_0 = 0, eta_0 = 1, eta_{t+1} = 1 / sqrt(1 + t),
+ *     c_{t+1/2} = c_t + (tangent-plane estimate on u + c_t chi_patch),
+ *     c_{t+1} = (c_t + c_{t+1/2} + eta_t alpha s f*) / (2 + eta_t alpha s),
+ * s = pixels of the patch in the image, f* = their mean of f - u.  The estimate
+ * uses the 8 planes of every ring r = 1 .. 2^(j-1) around the patch centre
+ * (chords W-E, N-S, NW-SE, NE-SW through the centre, each with either ring
+ * pixel perpendicular to it; 2^(j+2) planes on level j): the mean of the
+ * signed distances from the centre point to the planes for mean curvature
+ * (eq. (c-sol1)), or, for Gaussian curvature, the distance to the plane whose
+ * normal curvature d / ds^2 (ds^2 = squared 3-D half chord) is, of the smallest
+ * and the largest, the one of smaller magnitude (Proposition 2).  A patch's
+ * update reads pixels at most one pixel outside it, so patches of one colour
+ * do not interact.  These updates do not minimise F (eq. MCM / GCM) exactly;
+ * F is still what mg_fbs_energy reports and the energy stopping rule uses.
+ * Buffer conventions, stream semantics and errors are those of mg_curv_*.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t height;       /* H >= 2 */
+    int32_t width;        /* W >= 2 */
+    double alpha;         /* data weight, finite and >= 0 */
+    int32_t curvature;    /* mg_curv_kind */
+    int32_t levels;       /* J in [1, 16]; the paper's experiments use 3 */
+    int32_t state_dtype;  /* mg_dtype of u and f; the updates are computed in FP64 */
+    int32_t steps;        /* FBS updates per patch, [1, 64]; 1 is the paper's t = 0 */
+    int32_t cycle;        /* 0: levels 1..J (half V-cycle), 1: then J-1..1 (full V-cycle) */
+    int32_t reserved;     /* must be 0 */
+} mg_fbs_params;
+
+typedef enum {
+    MG_STOP_ENERGY = 0,   /* |E_l - E_{l-1}| < tol |E_l| (Section 4) */
+    MG_STOP_RELERR_U = 1  /* ||u_l - u_{l-1}||_2 < tol ||u_l||_2 (Section 4, relErr(u)) */
+} mg_stop_rule;
+
+typedef struct mg_fbs_ctx mg_fbs_ctx;
+
+/* Defaults for an H x W image: alpha 20, mean curvature, J = 3, float state,
+ * one FBS step, half V-cycle. */
+void mg_fbs_default_params(mg_fbs_params *p, int32_t height, int32_t width);
+
+/* Validate, bind the current device and stream, and allocate two H x W state
+ * images (level-1 output and the previous iterate for relErr(u)) plus small
+ * per-patch tables.  Errors as mg_curv_init. */
+mg_status mg_fbs_init(const mg_fbs_params *params, void *hip_stream, mg_fbs_ctx **out);
+
+/* One V-cycle on u (in place); F(u) afterwards into *energy_after if non-null
+ * (then the call waits). */
+mg_status mg_fbs_vcycle(mg_fbs_ctx *ctx, void *u, const void *f, double *energy_after);
+
+/* All four colours of one level (1-based), in place.  Enqueued only. */
+mg_status mg_fbs_level(mg_fbs_ctx *ctx, void *u, const void *f, int32_t level);
+
+/* One colour of one level, in place.  Enqueued only. */
+mg_status mg_fbs_sweep(mg_fbs_ctx *ctx, void *u, const void *f, int32_t level, int32_t colour);
+
+/* F(u) of eq. MCM / GCM in FP64 (same kernel and order as mg_curv_energy). */
+mg_status mg_fbs_energy(mg_fbs_ctx *ctx, const void *u, const void *f, double *energy);
+
+/* V-cycles until the stopping rule `stop` (mg_stop_rule) holds with tolerance
+ * tol, or max_vcycles cycles; tol <= 0 runs exactly max_vcycles.  Outputs as
+ * mg_curv_solve (energy_trace holds F before and after every V-cycle).
+ * Returns MG_OK, MG_NOT_CONVERGED or an error. */
+mg_status mg_fbs_solve(mg_fbs_ctx *ctx, void *u, const void *f, double tol, int32_t max_vcycles, int32_t stop,
+                       int32_t *vcycles_done, double *final_energy, double *energy_trace);
+
+/* Release (NULL allowed; waits for the stream first). */
+void mg_fbs_destroy(mg_fbs_ctx *ctx);
+
+/* Last error of ctx, or of this thread's last failed mg_fbs_init (ctx NULL). */
+const char *mg_fbs_last_error(const mg_fbs_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,15 @@ class MgCurvParams(C.Structure):
                 ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32)]
 
 
+class MgFbsParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
+                ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
+                ("steps", C.c_int32), ("cycle", C.c_int32), ("reserved", C.c_int32)]
+
+
+MG_STOP_ENERGY, MG_STOP_RELERR_U = 0, 1
+
+
 class MgCurvError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -115,6 +124,26 @@ def _load() -> C.CDLL:
     L.mg_curv_destroy.argtypes = [vp]
     L.mg_curv_last_error.restype = C.c_char_p
     L.mg_curv_last_error.argtypes = [vp]
+    FP = C.POINTER(MgFbsParams)
+    L.mg_fbs_default_params.restype = None
+    L.mg_fbs_default_params.argtypes = [FP, C.c_int32, C.c_int32]
+    L.mg_fbs_init.restype = C.c_int
+    L.mg_fbs_init.argtypes = [FP, vp, C.POINTER(vp)]
+    L.mg_fbs_vcycle.restype = C.c_int
+    L.mg_fbs_vcycle.argtypes = [vp, vp, cvp, C.POINTER(C.c_double)]
+    L.mg_fbs_level.restype = C.c_int
+    L.mg_fbs_level.argtypes = [vp, vp, cvp, C.c_int32]
+    L.mg_fbs_sweep.restype = C.c_int
+    L.mg_fbs_sweep.argtypes = [vp, vp, cvp, C.c_int32, C.c_int32]
+    L.mg_fbs_energy.restype = C.c_int
+    L.mg_fbs_energy.argtypes = [vp, cvp, cvp, C.POINTER(C.c_double)]
+    L.mg_fbs_solve.restype = C.c_int
+    L.mg_fbs_solve.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.mg_fbs_destroy.restype = None
+    L.mg_fbs_destroy.argtypes = [vp]
+    L.mg_fbs_last_error.restype = C.c_char_p
+    L.mg_fbs_last_error.argtypes = [vp]
     return L
 
 
@@ -259,6 +288,107 @@ class Solver:
 
     def level(self, u, f, level):
         return mg_curv_level(self.ctx, self.params, u, f, level)
+
+
+# --- the paper's own local step (FBS with tangent-plane estimates) ------------------
+
+def _fcheck(status: int, ctx=None) -> int:
+    if status < 0:
+        raise MgCurvError(status, lib.mg_fbs_last_error(ctx).decode())
+    return status
+
+
+def fbs_default_params(height: int, width: int, **kw) -> MgFbsParams:
+    p = MgFbsParams()
+    lib.mg_fbs_default_params(C.byref(p), height, width)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def mg_fbs_init(params: MgFbsParams, stream=None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _fcheck(lib.mg_fbs_init(C.byref(params), C.c_void_p(_stream_handle(stream)), C.byref(ctx)))
+    return ctx
+
+
+def mg_fbs_vcycle(ctx, params, u, f, want_energy: bool = False):
+    e = C.c_double()
+    _fcheck(lib.mg_fbs_vcycle(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"),
+                              C.byref(e) if want_energy else None), ctx)
+    return e.value if want_energy else None
+
+
+def mg_fbs_level(ctx, params, u, f, level: int) -> None:
+    _fcheck(lib.mg_fbs_level(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), level), ctx)
+
+
+def mg_fbs_sweep(ctx, params, u, f, level: int, colour: int) -> None:
+    _fcheck(lib.mg_fbs_sweep(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), level, colour), ctx)
+
+
+def mg_fbs_energy(ctx, params, u, f) -> float:
+    e = C.c_double()
+    _fcheck(lib.mg_fbs_energy(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), C.byref(e)), ctx)
+    return e.value
+
+
+def mg_fbs_solve(ctx, params, u, f, tol: float = 1e-4, max_vcycles: int = 1000, stop: int = MG_STOP_RELERR_U,
+                 trace: bool = False):
+    done = C.c_int32()
+    fin = C.c_double()
+    buf = (C.c_double * (max_vcycles + 1))() if trace else None
+    st = _fcheck(lib.mg_fbs_solve(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), tol, max_vcycles,
+                                  stop, C.byref(done), C.byref(fin), buf), ctx)
+    out = {"status": st, "vcycles": done.value, "energy": fin.value}
+    if trace:
+        out["trace"] = [buf[k] for k in range(done.value + 1)]
+    return out
+
+
+def mg_fbs_destroy(ctx) -> None:
+    lib.mg_fbs_destroy(ctx)
+
+
+class FbsSolver:
+    """The paper's own local step on patches of side 2^j - 1: one context per image size."""
+
+    def __init__(self, height: int, width: int, alpha: float = 20.0, kind: int = MG_CURV_MEAN, levels: int = 3,
+                 dtype=torch.float32, steps: int = 1, cycle: int = 0, stream=None):
+        self.params = fbs_default_params(height, width, alpha=float(alpha), curvature=int(kind), levels=int(levels),
+                                         state_dtype=MG_F64 if dtype == torch.float64 else MG_F32,
+                                         steps=int(steps), cycle=int(cycle))
+        self.dtype = dtype
+        self.levels = int(levels)
+        self.ctx = mg_fbs_init(self.params, stream)
+
+    def close(self):
+        if self.ctx:
+            mg_fbs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vcycle(self, u, f, want_energy=False):
+        return mg_fbs_vcycle(self.ctx, self.params, u, f, want_energy)
+
+    def level(self, u, f, level):
+        return mg_fbs_level(self.ctx, self.params, u, f, level)
+
+    def sweep(self, u, f, level, colour):
+        return mg_fbs_sweep(self.ctx, self.params, u, f, level, colour)
+
+    def energy(self, u, f):
+        return mg_fbs_energy(self.ctx, self.params, u, f)
+
+    def solve(self, u, f, tol=1e-4, max_vcycles=1000, stop=MG_STOP_RELERR_U, trace=False):
+        return mg_fbs_solve(self.ctx, self.params, u, f, tol, max_vcycles, stop, trace)
 
 
 # --- batched images ----------------------------------------------------------------

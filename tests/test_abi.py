@@ -142,3 +142,63 @@ def test_batch_no_device(lib):
     arr = _batch_params(lib, [(32, 40), (64, 64)])
     b = C.c_void_p()
     assert lib.mg_curv_batch_init(arr, 2, None, C.byref(b)) == -5
+
+
+class FbsParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
+                ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
+                ("steps", C.c_int32), ("cycle", C.c_int32), ("reserved", C.c_int32)]
+
+
+def _fbs(lib):
+    lib.mg_fbs_init.restype = C.c_int
+    lib.mg_fbs_init.argtypes = [C.POINTER(FbsParams), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.mg_fbs_default_params.argtypes = [C.POINTER(FbsParams), C.c_int32, C.c_int32]
+    lib.mg_fbs_last_error.restype = C.c_char_p
+    lib.mg_fbs_last_error.argtypes = [C.c_void_p]
+    for name in ("mg_fbs_vcycle", "mg_fbs_energy", "mg_fbs_sweep", "mg_fbs_level", "mg_fbs_solve"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+def test_fbs_params_struct_layout(lib):
+    _fbs(lib)
+    assert C.sizeof(FbsParams) == 40
+    p = FbsParams()
+    lib.mg_fbs_default_params(C.byref(p), 64, 48)
+    assert (p.height, p.width, p.alpha, p.curvature, p.levels, p.state_dtype) == (64, 48, 20.0, 0, 3, 0)
+    assert (p.steps, p.cycle, p.reserved) == (1, 0, 0)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("height", 1, -2), ("width", 0, -2), ("alpha", -1.0, -1), ("alpha", float("nan"), -1),
+    ("curvature", 2, -1), ("state_dtype", 7, -3), ("levels", 0, -1), ("levels", 17, -1),
+    ("steps", 0, -1), ("steps", 65, -1), ("cycle", 2, -1), ("reserved", 1, -1),
+])
+def test_fbs_invalid_params_rejected_before_device(lib, field, value, status):
+    _fbs(lib)
+    p = FbsParams()
+    lib.mg_fbs_default_params(C.byref(p), 64, 64)
+    setattr(p, field, value)
+    ctx = C.c_void_p(1234)
+    assert lib.mg_fbs_init(C.byref(p), None, C.byref(ctx)) == status
+    assert not ctx.value
+    assert lib.mg_fbs_last_error(None)
+
+
+def test_fbs_null_arguments_and_no_device(lib):
+    import torch
+    _fbs(lib)
+    ctx = C.c_void_p()
+    assert lib.mg_fbs_init(None, None, C.byref(ctx)) == -1
+    assert lib.mg_fbs_vcycle(None, None, None, None) == -1
+    assert lib.mg_fbs_energy(None, None, None, None) == -1
+    assert lib.mg_fbs_sweep(None, None, None, 1, 0) == -1
+    assert lib.mg_fbs_level(None, None, None, 1) == -1
+    lib.mg_fbs_destroy(None)
+    if torch.cuda.is_available():
+        return
+    p = FbsParams()
+    lib.mg_fbs_default_params(C.byref(p), 64, 64)
+    assert lib.mg_fbs_init(C.byref(p), None, C.byref(ctx)) == -5
+    assert b"device" in lib.mg_fbs_last_error(None).lower()

@@ -1,0 +1,211 @@
+"""GPU parity of the paper's own local step (mg_fbs_*, through the C ABI) against the FBS
+oracle.
+
+Tolerances, derived from the arithmetic: both sides compute every update in FP64 from the
+same inputs.  They differ in how a plane distance is formed (a cross product on the CPU, the
+closed form of the chord geometry on the GPU) and in summation order, about 1e-16 relative
+per term; the update is a smooth function of the inputs (for Gaussian curvature, piecewise
+smooth: the selected plane changes only where two normal curvatures tie to within rounding),
+so a sweep or a level agrees to <= 1e-11 relative to the intensity scale and a few V-cycles
+to <= 1e-9.  In float state both round the same FP64 value to float, so results agree to an
+ulp except where that value lies within rounding of a float midpoint.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import FbsOracle
+from synth import noisy_image
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2204_07921_amd import mgcurv
+    return mgcurv
+
+
+def dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _inputs(h, w, seed, scale, dtype, perturb=0.0):
+    """Seeded synthetic image at intensity scale `scale` (1 or 255) and a perturbed start."""
+    f, _ = noisy_image(h, w, seed, 0.08, dtype=np.float64)
+    f = scale * f
+    u = f.copy()
+    if perturb:
+        u = u + scale * perturb * np.random.default_rng(seed + 5).standard_normal(u.shape)
+    if dtype == torch.float32:
+        f = f.astype(np.float32).astype(np.float64)
+        u = u.astype(np.float32).astype(np.float64)
+    return f, u
+
+
+# (alpha, intensity scale): the [0, 1] setting and the paper's [0, 255] one
+REGIMES = [(20.0, 1.0), (0.05, 255.0)]
+
+
+def _compare(gpu, ref, scale, dtype, what):
+    if dtype == torch.float64:
+        err = np.max(np.abs(gpu - ref))
+        assert err <= 1e-11 * scale, f"{what}: max |du| = {err:.3e}"
+    else:
+        ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+        bad = np.abs(gpu - ref) > ulp
+        assert bad.sum() <= max(1, bad.size // 1000), f"{what}: {bad.sum()} pixels differ by more than an ulp"
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("regime", REGIMES)
+def test_every_sweep_matches_oracle(mg, dtype, kind, regime):
+    """Teacher-forced: from one shared state, each colour sweep of each level."""
+    alpha, scale = regime
+    h, w, J = 45, 70, 4
+    f, u0 = _inputs(h, w, 3, scale, dtype, perturb=0.05)
+    o = FbsOracle(h, w, alpha, kind, levels=J, steps=2, round_f32=dtype == torch.float32)
+    s = mg.FbsSolver(h, w, alpha, kind, levels=J, dtype=dtype, steps=2)
+    fd = dev(f, dtype)
+    for level in range(1, J + 1):
+        for colour in range(4):
+            _case(f"fbs sweep {h}x{w} kind={kind} alpha={alpha} {dtype} level={level} colour={colour}")
+            ref = u0.copy()
+            o.sweep(ref, f, level, colour)
+            ud = dev(u0, dtype)
+            s.sweep(ud, fd, level, colour)
+            _compare(host(ud), ref, scale, dtype, f"level {level} colour {colour}")
+            assert not np.array_equal(ref, u0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("shape", [(2, 2), (3, 40), (33, 65), (97, 130), (256, 256)])
+def test_levels_match_oracle(mg, dtype, kind, shape):
+    """Each level's four colours in one call (the fused pixel-level kernel at level 1), from a
+    shared state, on ragged shapes spanning several 32 x 64 tiles and tiny images."""
+    h, w = shape
+    alpha, scale = REGIMES[1]
+    J = 4
+    f, u0 = _inputs(h, w, 11, scale, dtype, perturb=0.03)
+    o = FbsOracle(h, w, alpha, kind, levels=J, round_f32=dtype == torch.float32)
+    s = mg.FbsSolver(h, w, alpha, kind, levels=J, dtype=dtype)
+    fd = dev(f, dtype)
+    for level in range(1, J + 1):
+        _case(f"fbs level {h}x{w} kind={kind} {dtype} level={level}")
+        ref = u0.copy()
+        o.level(ref, f, level)
+        ud = dev(u0, dtype)
+        s.level(ud, fd, level)
+        _compare(host(ud), ref, scale, dtype, f"level {level}")
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("cycle,steps,J", [(0, 1, 3), (1, 1, 3), (0, 15, 3), (0, 1, 7)])
+def test_vcycles_free_running(mg, kind, cycle, steps, J):
+    """Several V-cycles without re-synchronising the state (FP64)."""
+    h, w = 120, 97
+    alpha, scale = REGIMES[1]
+    f, _ = _inputs(h, w, 21, scale, torch.float64)
+    o = FbsOracle(h, w, alpha, kind, levels=J, steps=steps, cycle=cycle)
+    s = mg.FbsSolver(h, w, alpha, kind, levels=J, dtype=torch.float64, steps=steps, cycle=cycle)
+    _case(f"fbs free-running kind={kind} cycle={cycle} steps={steps} J={J}")
+    ref = f.copy()
+    ud, fd = dev(f, torch.float64), dev(f, torch.float64)
+    for v in range(5):
+        o.vcycle(ref, f)
+        e = s.vcycle(ud, fd, want_energy=True)
+        err = np.max(np.abs(host(ud) - ref))
+        assert err <= 1e-9 * scale, f"V-cycle {v + 1}: max |du| = {err:.3e}"
+        assert e == pytest.approx(o.energy(ref, f), rel=1e-11)
+
+
+@pytest.mark.parametrize("stop", [0, 1])
+def test_solve_stopping_rules(mg, stop):
+    h, w = 80, 72
+    alpha, scale = REGIMES[1]
+    f, _ = _inputs(h, w, 31, scale, torch.float64)
+    tol = 1e-6 if stop == 0 else 1e-4
+    o = FbsOracle(h, w, alpha, 0, levels=3)
+    ref = f.copy()
+    n_ref, tr_ref = o.solve(ref, f, tol=tol, max_vcycles=300, stop=stop)
+    s = mg.FbsSolver(h, w, alpha, 0, levels=3, dtype=torch.float64)
+    ud, fd = dev(f, torch.float64), dev(f, torch.float64)
+    _case(f"fbs solve stop={stop}")
+    res = s.solve(ud, fd, tol=tol, max_vcycles=300, stop=stop, trace=True)
+    assert res["vcycles"] == n_ref
+    assert np.allclose(res["trace"], tr_ref, rtol=1e-10, atol=0)
+    assert np.max(np.abs(host(ud) - ref)) <= 1e-8 * scale
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_full_size_vcycle_1024(mg, dtype, kind):
+    """The bench's workload shape and launch configuration: one V-cycle at 1024 x 1024, J = 3,
+    every pixel compared with the oracle."""
+    n = 1024
+    alpha, scale = REGIMES[1]
+    f, _ = _inputs(n, n, 41, scale, dtype)
+    o = FbsOracle(n, n, alpha, kind, levels=3, round_f32=dtype == torch.float32, threads=8)
+    ref = f.copy()
+    o.vcycle(ref, f)
+    s = mg.FbsSolver(n, n, alpha, kind, levels=3, dtype=dtype)
+    ud, fd = dev(f, dtype), dev(f, dtype)
+    _case(f"fbs 1024 vcycle kind={kind} {dtype}")
+    s.vcycle(ud, fd)
+    _compare(host(ud), ref, scale, dtype, "1024 V-cycle")
+
+
+def test_coarse_patch_larger_than_image(mg):
+    """J beyond the image: the coarsest patch covers the image and its centre lies outside."""
+    h, w = 40, 23
+    alpha, scale = REGIMES[0]
+    f, u0 = _inputs(h, w, 51, scale, torch.float64, perturb=0.1)
+    for kind in (0, 1):
+        o = FbsOracle(h, w, alpha, kind, levels=8, steps=3)
+        s = mg.FbsSolver(h, w, alpha, kind, levels=8, dtype=torch.float64, steps=3)
+        _case(f"fbs J=8 on {h}x{w} kind={kind}")
+        ref = u0.copy()
+        o.vcycle(ref, f)
+        ud, fd = dev(u0, torch.float64), dev(f, torch.float64)
+        s.vcycle(ud, fd)
+        _compare(host(ud), ref, scale, torch.float64, "J=8")
+
+
+def test_deterministic(mg):
+    h, w = 300, 260
+    alpha, scale = REGIMES[1]
+    f, _ = _inputs(h, w, 61, scale, torch.float32)
+    s = mg.FbsSolver(h, w, alpha, 1, levels=5, dtype=torch.float32, steps=3)
+    fd = dev(f, torch.float32)
+    outs = []
+    for _ in range(2):
+        ud = dev(f, torch.float32)
+        for _ in range(3):
+            s.vcycle(ud, fd)
+        outs.append(host(ud))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_fixed_point_and_errors(mg):
+    h, w = 50, 61
+    g = np.full((h, w), 0.375)
+    s = mg.FbsSolver(h, w, 20.0, 0, levels=4, dtype=torch.float64, steps=2)
+    ud, gd = dev(g, torch.float64), dev(g, torch.float64)
+    s.vcycle(ud, gd)
+    assert np.array_equal(host(ud), g)
+    with pytest.raises(mg.MgCurvError):
+        s.level(ud, gd, 5)
+    with pytest.raises(mg.MgCurvError):
+        s.sweep(ud, gd, 1, 4)
+    with pytest.raises(mg.MgCurvError):
+        s.vcycle(ud, ud)
