@@ -17,16 +17,20 @@
 // take the value of the nearest image pixel (the prolonged domain).
 //
 // Data flow per V-cycle (state dtype T = float or double, local math in FP64):
-//   level 1 (b = 1): one launch; a workgroup loads a 32 x 64 tile of u with a
-//     4-pixel halo into LDS and runs the four colour sweeps there, shrinking the
+//   level 1 (b = 1): one launch; a workgroup loads a 64 x 64 tile (32 x 64 for
+//     double) of u and f with a 4-pixel halo into LDS and runs the four colour
+//     sweeps there, shrinking the
 //     region it trusts by one pixel per colour (each sweep reads one pixel
 //     around the updated pixel), then writes the tile to the other buffer.
 //     Every pixel is read once and written once per level.
-//   level j >= 2: (1) per patch and row chunk, FP64 partial sums of f - u over
-//     the patch (the patch's own pixels do not change before its colour) and
-//     zeroed pending corrections; (2) four colour launches, a lane group per
-//     patch holding the rings, reading tap values as u + the pending correction
-//     of the tap's patch (rounded to T); (3) u <- u + c_patch.
+//   levels with patch side 3 and 7: one launch each, the same scheme with a
+//     tile of patches and a halo of 4 patches (corrections kept in LDS); the
+//     sums of f over their patches come from one pass over f per V-cycle.
+//   larger patches: (1) per patch and row chunk, FP64 partial sums of f - u over
+//     the patch (the patch's own pixels do not change before its colour);
+//     (2) four colour launches, a lane group per patch holding the rings,
+//     reading tap values as u + the correction of the tap's patch (rounded to T)
+//     when that patch's colour came earlier in the level; (3) u <- u + c_patch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -57,8 +61,8 @@ __device__ __forceinline__ void chord(double ua, double ub, double l, double l2,
     const double s = l2 + e * e;
     const double num = l * (h - uo);
     const double g0 = t0 - h, g1 = t1 - h;
-    d0 = num / sqrt(s + g0 * g0);
-    d1 = num / sqrt(s + g1 * g1);
+    d0 = num * rsqrt(s + g0 * g0);
+    d1 = num * rsqrt(s + g1 * g1);
     ds2 = s;
 }
 
@@ -79,9 +83,12 @@ __device__ __forceinline__ void ring_accumulate(double uo, const double (&v)[8],
 #pragma unroll
         for (int k = 0; k < 8; ++k) sum += d[k];
     } else {
+        double inv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) inv[m] = 1.0 / s[m];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const double kap = d[k] / s[k >> 1];
+            const double kap = d[k] * inv[k >> 1];
             const int idx = base + k;
             if (kap < g.kmin || (kap == g.kmin && idx < g.imin)) { g.kmin = kap; g.dmin = d[k]; g.imin = idx; }
             if (kap > g.kmax || (kap == g.kmax && idx < g.imax)) { g.kmax = kap; g.dmax = d[k]; g.imax = idx; }
@@ -116,11 +123,68 @@ __device__ __forceinline__ constexpr int ring_dj(int k)
     return k < 2 ? (k == 0 ? -1 : 1) : (k < 4 ? 0 : (k == 4 ? -1 : (k == 5 ? 1 : (k == 6 ? 1 : -1))));
 }
 
+// Visit an nr x nc region: a wave covers 64 consecutive columns of a row (the
+// accesses coalesce), NT / 64 rows per pass, K rows' loads in flight per thread
+// before the first store; no integer division.
+template <int NT, int K, class Ld, class St>
+__device__ __forceinline__ void copy2d(int nr, int nc, const Ld& ld, const St& st)
+{
+    constexpr int RS = NT / 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int c = tx; c < nc; c += 64) {
+        for (int r0 = ty; r0 < nr; r0 += RS * K) {
+            decltype(ld(0, 0)) tmp[K];
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const int r = r0 + m * RS;
+                if (r < nr) tmp[m] = ld(r, c);
+            }
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const int r = r0 + m * RS;
+                if (r < nr) st(r, c, tmp[m]);
+            }
+        }
+    }
+}
+
+// Copy an nr x nc region of u and of f into two LDS tiles with the mapping of
+// copy2d, the loads of K rows of both arrays in flight per thread.
+template <int NT, int K, class T, class Idx>
+__device__ __forceinline__ void copy_pair(int nr, int nc, const T* __restrict__ u, const T* __restrict__ f, int W,
+                                          int r_img, int c_img, T* su, T* sf, const Idx& lds_index)
+{
+    constexpr int RS = NT / 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int c = tx; c < nc; c += 64) {
+        for (int r0 = ty; r0 < nr; r0 += RS * K) {
+            T a[K], b[K];
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const int r = r0 + m * RS;
+                if (r < nr) {
+                    const size_t g = (size_t)(r_img + r) * W + (c_img + c);
+                    a[m] = u[g];
+                    b[m] = f[g];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < K; ++m) {
+                const int r = r0 + m * RS;
+                if (r < nr) {
+                    const int l = lds_index(r, c);
+                    su[l] = a[m];
+                    sf[l] = b[m];
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Level 1 (b = 1): the four colours of the level in one launch.
 // ---------------------------------------------------------------------------
-constexpr int PT_H = 32, PT_W = 64, PHALO = 4;
-constexpr int PL_H = PT_H + 2 * PHALO, PL_W = PT_W + 2 * PHALO;
+constexpr int PHALO = 4;
 
 // FBS correction of pixel (i, j) from its clamped 3x3 neighbourhood `at(ii, jj)`.
 template <int KIND, class At>
@@ -151,45 +215,48 @@ __device__ __forceinline__ double pixel_correction(const At& at, int i, int j, i
     return c;
 }
 
-template <typename T, int KIND>
-__global__ __launch_bounds__(256) void fbs_pixel_level_kernel(const T* __restrict__ uin, T* __restrict__ uout,
-                                                              const T* __restrict__ f, int H, int W, double alpha,
-                                                              int steps)
+template <typename T, int KIND, int TH, int TW, int NT>
+__global__ __launch_bounds__(NT) void fbs_pixel_level_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                             const T* __restrict__ f, int H, int W, double alpha,
+                                                             int steps)
 {
-    __shared__ T su[PL_H * PL_W];
-    const int y0 = blockIdx.y * PT_H, x0 = blockIdx.x * PT_W;
+    constexpr int LW = TW + 2 * PHALO;
+    __shared__ T su[(TH + 2 * PHALO) * LW];
+    __shared__ T sf[(TH + 2 * PHALO) * LW];
+    const int y0 = blockIdx.y * TH, x0 = blockIdx.x * TW;
     const int ly = y0 - PHALO, lx = x0 - PHALO;
-    const int r_lo = max(0, ly), r_hi = min(H, y0 + PT_H + PHALO);
-    const int c_lo = max(0, lx), c_hi = min(W, x0 + PT_W + PHALO);
+    const int r_lo = max(0, ly), r_hi = min(H, y0 + TH + PHALO);
+    const int c_lo = max(0, lx), c_hi = min(W, x0 + TW + PHALO);
     const int nr = r_hi - r_lo, nc = c_hi - c_lo;
-    for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
-        const int i = r_lo + t / nc, j = c_lo + t % nc;
-        su[(i - ly) * PL_W + (j - lx)] = uin[(size_t)i * W + j];
-    }
+    // u and f of the loaded region (f is read by the pixels solved, all inside it)
+    copy_pair<NT, 4>(nr, nc, uin, f, W, r_lo, c_lo, su, sf,
+                      [&](int r, int c) { return (r_lo + r - ly) * LW + (c_lo + c - lx); });
     __syncthreads();
-    auto at = [&](int ii, int jj) { return (double)su[(ii - ly) * PL_W + (jj - lx)]; };
+    auto at = [&](int ii, int jj) { return (double)su[(ii - ly) * LW + (jj - lx)]; };
     for (int k = 0; k < 4; ++k) {
         // region still exact after sweep k: k + 1 pixels inside every tile edge that is not an image edge
         const int vr0 = r_lo == 0 ? 0 : r_lo + k + 1, vr1 = r_hi == H ? H : r_hi - k - 1;
         const int vc0 = c_lo == 0 ? 0 : c_lo + k + 1, vc1 = c_hi == W ? W : c_hi - k - 1;
         const int i0 = vr0 + ((vr0 & 1) != (k >> 1)), j0 = vc0 + ((vc0 & 1) != (k & 1));
         const int ni = i0 < vr1 ? (vr1 - i0 + 1) / 2 : 0, nj = j0 < vc1 ? (vc1 - j0 + 1) / 2 : 0;
-        for (int t = threadIdx.x; t < ni * nj; t += blockDim.x) {
+        for (int t = threadIdx.x; t < ni * nj; t += NT) {
             const int i = i0 + 2 * (t / nj), j = j0 + 2 * (t % nj);
             const double uo = at(i, j);
-            const double fs = (double)f[(size_t)i * W + j] - uo;
+            const double fs = (double)sf[(i - ly) * LW + (j - lx)] - uo;
             const double c = pixel_correction<KIND>(at, i, j, H, W, fs, alpha, steps);
             // pixels of one colour read only other colours (or themselves), so the write is safe
-            su[(i - ly) * PL_W + (j - lx)] = (T)(uo + c);
+            su[(i - ly) * LW + (j - lx)] = (T)(uo + c);
         }
         __syncthreads();
     }
-    const int o_r1 = min(H, y0 + PT_H), o_c1 = min(W, x0 + PT_W);
-    for (int t = threadIdx.x; t < PT_H * PT_W; t += blockDim.x) {
-        const int i = y0 + t / PT_W, j = x0 + t % PT_W;
-        if (i < o_r1 && j < o_c1) uout[(size_t)i * W + j] = su[(i - ly) * PL_W + (j - lx)];
-    }
+    const int onr = min(H, y0 + TH) - y0, onc = min(W, x0 + TW) - x0;
+    copy2d<NT, 4>(onr, onc, [&](int r, int c) { return su[(y0 + r - ly) * LW + (x0 + c - lx)]; },
+                  [&](int r, int c, T x) { uout[(size_t)(y0 + r) * W + (x0 + c)] = x; });
 }
+
+// Tile of the pixel level per state type: (rows, columns, threads).
+template <typename T> struct PixelTile { static constexpr int TH = 64, TW = 64, NT = 512; };
+template <> struct PixelTile<double> { static constexpr int TH = 32, TW = 64, NT = 512; };
 
 // One colour of level 1, in place (for single-sweep inspection).
 template <typename T, int KIND>
@@ -211,22 +278,161 @@ __global__ __launch_bounds__(256) void fbs_pixel_colour_kernel(T* __restrict__ u
 // Levels j >= 2.
 // ---------------------------------------------------------------------------
 
-// Partial sums of f - u per (patch, row chunk), L lanes per group; chunk 0 of
-// every patch also zeroes the patch's pending correction.
+// A whole coarse level with small patches (side B) in one launch.  A workgroup
+// owns TP x TP patches and loads them with a halo of HALO patches into LDS;
+// colour k is solved for the patches at least k + 1 patches inside every
+// loaded edge that is not an image edge (a patch reads at most one pixel of
+// its neighbours and their corrections of earlier colours), so after the four
+// colours the owned patches are exact.  A group of G = (B + 1) / 2 lanes
+// solves one patch (lane l holds ring l + 1).  Corrections live in LDS; the
+// owned pixels are written to the other buffer with their patch's correction.
+template <typename T, int KIND, int B, int TP, int NT>
+__global__ __launch_bounds__(NT) void fbs_patch_level_kernel(const T* __restrict__ uin, T* __restrict__ uout,
+                                                             const double* __restrict__ fsum, int H, int W, int mj,
+                                                             int nj, double alpha, int steps)
+{
+    constexpr int HALO = 4, LP = TP + 2 * HALO, LPX = LP * B, R = (B + 1) / 2, G = R;
+    __shared__ T su[LPX * LPX];
+    __shared__ double sc[LP * LP];    // corrections of the loaded patches
+    __shared__ double ss[LP * LP];    // sums of f - u over the loaded patches
+    const int P0 = blockIdx.y * TP, Q0 = blockIdx.x * TP;
+    const int lp0 = P0 - HALO, lq0 = Q0 - HALO;
+    const int pa = max(0, lp0), pb = min(mj, P0 + TP + HALO);
+    const int qa = max(0, lq0), qb = min(nj, Q0 + TP + HALO);
+    const int ly = lp0 * B, lx = lq0 * B;
+    const int ra = pa * B, rb = min(H, pb * B), ca = qa * B, cb = min(W, qb * B);
+    copy2d<NT, 4>(rb - ra, cb - ca, [&](int r, int c) { return uin[(size_t)(ra + r) * W + (ca + c)]; },
+                  [&](int r, int c, T x) { su[(ra + r - ly) * LPX + (ca + c - lx)] = x; });
+    for (int t = threadIdx.x; t < LP * LP; t += NT) sc[t] = 0.0;
+    __syncthreads();
+    // sum of f - u over each patch as (sum of f) - (sum of u): the sums of f come
+    // from fbs_fsums_kernel, the patch's pixels do not change before its colour
+    for (int t = threadIdx.x; t < LP * LP; t += NT) {
+        const int pl = t / LP, ql = t - pl * LP, p = lp0 + pl, q = lq0 + ql;
+        if (p < pa || p >= pb || q < qa || q >= qb) continue;
+        double su_sum = 0.0;
+        for (int i = p * B; i < min(p * B + B, H); ++i)
+            for (int j = q * B; j < min(q * B + B, W); ++j) su_sum += (double)su[(i - ly) * LPX + (j - lx)];
+        ss[t] = fsum[(size_t)p * nj + q] - su_sum;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % G;
+    for (int k = 0; k < 4; ++k) {
+        const int vp0 = pa == 0 ? 0 : pa + k + 1, vp1 = pb == mj ? mj : pb - k - 1;
+        const int vq0 = qa == 0 ? 0 : qa + k + 1, vq1 = qb == nj ? nj : qb - k - 1;
+        const int p0 = vp0 + ((vp0 & 1) != (k >> 1)), q0 = vq0 + ((vq0 & 1) != (k & 1));
+        const int np = p0 < vp1 ? (vp1 - p0 + 1) / 2 : 0, nq = q0 < vq1 ? (vq1 - q0 + 1) / 2 : 0;
+        for (int g = threadIdx.x / G; g < np * nq; g += NT / G) {
+            const int p = p0 + 2 * (g / nq), q = q0 + 2 * (g % nq);
+            const int r0 = p * B, r1 = min(r0 + B, H), c0 = q * B, c1 = min(c0 + B, W);
+            const double s = (double)((r1 - r0) * (c1 - c0)), fs = ss[(p - lp0) * LP + (q - lq0)] / s;
+            const int oi = r0 + R - 1, oj = c0 + R - 1;
+            auto value = [&](int i, int j, double shift) {
+                const int ci = clampi(i, 0, H - 1), cj = clampi(j, 0, W - 1);
+                const double x = (double)su[(ci - ly) * LPX + (cj - lx)];
+                const int tp = ci / B, tq = cj / B;
+                if (tp == p && tq == q) return x + shift;
+                const double cp = sc[(tp - lp0) * LP + (tq - lq0)];
+                return cp != 0.0 ? (double)(T)(x + cp) : x;
+            };
+            // patches whose taps stay inside the image: ring r < R lies in the patch,
+            // ring R in the neighbour (p + di, q + dj); same values as `value`
+            const bool interior = r0 >= 1 && c0 >= 1 && r0 + B < H && c0 + B < W;
+            const int r = lane + 1;
+            auto ring_value = [&](int m, double shift) {
+                const int di = ring_di(m), dj = ring_dj(m);
+                if (!interior) return value(oi + r * di, oj + r * dj, shift);
+                const double x = (double)su[(oi + r * di - ly) * LPX + (oj + r * dj - lx)];
+                if (r < R) return x + shift;
+                const double cp = sc[(p + di - lp0) * LP + (q + dj - lq0)];
+                return cp != 0.0 ? (double)(T)(x + cp) : x;
+            };
+            double c = 0.0, eta = 1.0;
+            for (int t = 0; t < steps; ++t) {
+                double sum = 0.0;
+                GcAcc acc = gc_empty();
+                const double uo = value(oi, oj, c);
+                double v[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) v[m] = ring_value(m, c);
+                ring_accumulate<KIND>(uo, v, (double)r, 8 * (r - 1), sum, acc);
+                double est;
+                if constexpr (KIND == 0) {
+#pragma unroll
+                    for (int off = 1; off < G; off <<= 1) sum += __shfl_xor(sum, off, 64);
+                    est = sum / (double)(8 * R);
+                } else {
+#pragma unroll
+                    for (int off = 1; off < G; off <<= 1) {
+                        const double ok = __shfl_xor(acc.kmin, off, 64), od = __shfl_xor(acc.dmin, off, 64);
+                        const int oid = __shfl_xor(acc.imin, off, 64);
+                        if (ok < acc.kmin || (ok == acc.kmin && oid < acc.imin)) { acc.kmin = ok; acc.dmin = od; acc.imin = oid; }
+                        const double xk = __shfl_xor(acc.kmax, off, 64), xd = __shfl_xor(acc.dmax, off, 64);
+                        const int xid = __shfl_xor(acc.imax, off, 64);
+                        if (xk > acc.kmax || (xk == acc.kmax && xid < acc.imax)) { acc.kmax = xk; acc.dmax = xd; acc.imax = xid; }
+                    }
+                    est = gc_choice(acc);
+                }
+                c = backward(c, c + est, eta * alpha * s, fs);
+                eta = 1.0 / sqrt(1.0 + (double)t);
+            }
+            if (lane == 0) sc[(p - lp0) * LP + (q - lq0)] = c;
+        }
+        __syncthreads();
+    }
+    const int o_r0 = P0 * B, o_c0 = Q0 * B;
+    const int onr = min(H, (P0 + TP) * B) - o_r0, onc = min(W, (Q0 + TP) * B) - o_c0;
+    copy2d<NT, 4>(onr, onc,
+                  [&](int r, int cc) {
+                      const int i = o_r0 + r, j = o_c0 + cc;
+                      const T x = su[(i - ly) * LPX + (j - lx)];
+                      const double c = sc[(i / B - lp0) * LP + (j / B - lq0)];
+                      return c != 0.0 ? (T)((double)x + c) : x;
+                  },
+                  [&](int r, int cc, T x) { uout[(size_t)(o_r0 + r) * W + (o_c0 + cc)] = x; });
+}
+
+// Sums of f over the patches of side 3 and of side 7 (row-major within a patch):
+// a workgroup loads a 42 x 42 tile of f, which holds 14 x 14 and 6 x 6 whole patches.
+template <typename T>
+__global__ __launch_bounds__(256) void fbs_fsums_kernel(const T* __restrict__ f, int H, int W, double* __restrict__ fsum3,
+                                                        double* __restrict__ fsum7)
+{
+    constexpr int TS = 42;
+    __shared__ T sf[TS * TS];
+    const int y0 = blockIdx.y * TS, x0 = blockIdx.x * TS;
+    const int nr = min(TS, H - y0), nc = min(TS, W - x0);
+    copy2d<256, 4>(nr, nc, [&](int r, int c) { return f[(size_t)(y0 + r) * W + (x0 + c)]; },
+                   [&](int r, int c, T x) { sf[r * TS + c] = x; });
+    __syncthreads();
+    const int n3 = (W + 2) / 3, n7 = (W + 6) / 7;
+    for (int t = threadIdx.x; t < 14 * 14 + 6 * 6; t += 256) {
+        const int B = t < 196 ? 3 : 7, k = t < 196 ? t : t - 196, per = TS / B;
+        const int pl = k / per, ql = k - pl * per;
+        if (pl * B >= nr || ql * B >= nc) continue;
+        double S = 0.0;
+        for (int r = pl * B; r < min(pl * B + B, nr); ++r)
+            for (int c = ql * B; c < min(ql * B + B, nc); ++c) S += (double)sf[r * TS + c];
+        const int p = y0 / B + pl, q = x0 / B + ql;
+        if (B == 3) fsum3[(size_t)p * n3 + q] = S;
+        else fsum7[(size_t)p * n7 + q] = S;
+    }
+}
+
+// Partial sums of f - u per (patch, row chunk), L lanes per group (patches too
+// large for the colour kernel's own groups to sum).
 template <typename T, int L>
 __global__ __launch_bounds__(256) void fbs_sums_kernel(const T* __restrict__ u, const T* __restrict__ f, int H, int W,
                                                        int b, int nj, int ngroups, int nchunk, int rows_per,
-                                                       double* __restrict__ psums, double* __restrict__ cpend)
+                                                       double* __restrict__ psums)
 {
     __shared__ double lds[4];
     const int g = (int)((blockIdx.x * blockDim.x + threadIdx.x) / L);
     const int lane = threadIdx.x % L;
     const bool live = g < ngroups;
     double acc = 0.0;
-    int patch = 0, k = 0;
     if (live) {
-        patch = g / nchunk;
-        k = g - patch * nchunk;
+        const int patch = g / nchunk, k = g - patch * nchunk;
         const int p = patch / nj, q = patch - p * nj;
         const int r0 = p * b + k * rows_per, r1 = min(min(r0 + rows_per, p * b + b), H);
         const int c0 = q * b, c1 = min(c0 + b, W), w = c1 - c0;
@@ -246,18 +452,20 @@ __global__ __launch_bounds__(256) void fbs_sums_kernel(const T* __restrict__ u, 
         __syncthreads();
         acc = (lds[0] + lds[1]) + (lds[2] + lds[3]);
     }
-    if (live && lane == 0) {
-        psums[g] = acc;
-        if (k == 0) cpend[patch] = 0.0;
-    }
+    if (live && lane == 0) psums[g] = acc;
 }
 
 // One colour of a coarse level: a group of G lanes per patch, lane l taking rings
-// l + 1, l + 1 + G, ...; the patch's correction goes to cpend.
+// l + 1, l + 1 + G, ...; the patch's correction goes to cpend.  A neighbour's
+// entry in cpend counts only if its colour was solved earlier in this pass
+// (solved_from <= colour' < colour); other entries are stale and read as 0.
+// With nchunk == 0 the group sums f - u over the patch itself, else it adds
+// the row-chunk partials of fbs_sums_kernel.
 template <typename T, int KIND, int G>
-__global__ __launch_bounds__(256) void fbs_patch_kernel(const T* __restrict__ u, int H, int W, int b, int mj, int nj,
-                                                        int colour, int nchunk, const double* __restrict__ psums,
-                                                        double* __restrict__ cpend, double alpha, int steps)
+__global__ __launch_bounds__(256) void fbs_patch_kernel(const T* __restrict__ u, const T* __restrict__ f, int H, int W,
+                                                        int b, int mj, int nj, int colour, int solved_from, int nchunk,
+                                                        const double* __restrict__ psums, double* __restrict__ cpend,
+                                                        double alpha, int steps)
 {
     const int R = (b + 1) / 2;
     const int pr = colour >> 1, pc = colour & 1;
@@ -269,8 +477,17 @@ __global__ __launch_bounds__(256) void fbs_patch_kernel(const T* __restrict__ u,
     const int oi = r0 + R - 1, oj = c0 + R - 1;
     const int patch = p * nj + q;
     double S = 0.0;
-    if (live)
+    if (nchunk == 0) {
+        const int w = c1 - c0, n = live ? (r1 - r0) * w : 0;
+        for (int t = lane; t < n; t += G) {
+            const size_t idx = (size_t)(r0 + t / w) * W + (c0 + t % w);
+            S += (double)f[idx] - (double)u[idx];
+        }
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) S += __shfl_xor(S, off, 64);
+    } else if (live) {
         for (int k = 0; k < nchunk; ++k) S += psums[(size_t)patch * nchunk + k];
+    }
     const double s = (double)((r1 - r0) * (c1 - c0));
     const double fs = S / s;
     // state value at a clamped position: u + pending correction of its patch (own patch: + shift)
@@ -279,7 +496,10 @@ __global__ __launch_bounds__(256) void fbs_patch_kernel(const T* __restrict__ u,
         const double x = (double)u[(size_t)ci * W + cj];
         const int dp = ci < r0 ? -1 : (ci >= r1 ? 1 : 0), dq = cj < c0 ? -1 : (cj >= c1 ? 1 : 0);
         if (dp == 0 && dq == 0) return x + shift;
-        const double cp = cpend[(size_t)(p + dp) * nj + (q + dq)];
+        const int np = p + dp, nq = q + dq;
+        const int ncol = 2 * (np & 1) + (nq & 1);
+        if (ncol < solved_from || ncol >= colour) return x;
+        const double cp = cpend[(size_t)np * nj + nq];
         return cp != 0.0 ? (double)(T)(x + cp) : x;
     };
     double c = 0.0, eta = 1.0;
@@ -318,17 +538,20 @@ __global__ __launch_bounds__(256) void fbs_patch_kernel(const T* __restrict__ u,
     if (live && lane == 0) cpend[patch] = c;
 }
 
-// dst <- src + c of the pixel's patch (rounded to T).  In place (src == dst)
-// only pixels with a nonzero correction are written.
+// dst <- src + c of the pixel's patch (rounded to T) for patches whose colour
+// lies in [cmin, cmax].  In place (src == dst) only pixels with a nonzero
+// correction are written.
 template <typename T>
 __global__ __launch_bounds__(256) void fbs_apply_kernel(const T* src, T* dst, int H, int W, int b, int nj,
-                                                        const double* __restrict__ cpend, int in_place)
+                                                        const double* __restrict__ cpend, int in_place, int cmin,
+                                                        int cmax)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= W) return;
     const int q = j / b;
     for (int i = blockIdx.y; i < H; i += gridDim.y) {
-        const double c = cpend[(size_t)(i / b) * nj + q];
+        const int p = i / b, col = 2 * (p & 1) + (q & 1);
+        const double c = (col >= cmin && col <= cmax) ? cpend[(size_t)p * nj + q] : 0.0;
         const size_t idx = (size_t)i * W + j;
         if (in_place) {
             if (c != 0.0) dst[idx] = (T)((double)src[idx] + c);
@@ -411,24 +634,51 @@ void patch_geometry(int H, int W, int b, int* mj, int* nj, int* nchunk, int* row
 // ---------------------------------------------------------------------------
 // Host runtime
 // ---------------------------------------------------------------------------
+namespace {
+
+// A captured V-cycle for one (u, f) pair.  what: 0 = V-cycle only; 1 = then
+// F(u) and a copy to the host mirror; 2 = copy of u to prev first, then the
+// V-cycle, F(u), the relErr(u) norms and the host copy.
+struct FbsGraph {
+    const void* u = nullptr;
+    const void* f = nullptr;
+    int what = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+constexpr int NGRAPHS = 4;
+
+}  // namespace
+
 struct mg_fbs_ctx {
     mg_fbs_params P;
     int device;
-    hipStream_t stream;
-    void* ping;        // H x W state image (level 1 writes here)
-    void* prev;        // H x W state image (relErr(u) stop rule)
-    double* psums;     // patch partial sums, max over coarse levels
-    double* cpend;     // pending corrections, max patches over coarse levels
-    double* epart;     // energy partials
-    double* npart;     // norm partials (2 * NORM_BLOCKS)
-    double* dev3;      // energy, ||u - prev||^2, ||u||^2
-    double* host3;     // pinned copy of dev3
+    hipStream_t stream;    // caller's stream: every launch and graph replay goes here
+    hipStream_t gstream;   // own stream, used only to capture graphs (default priority)
+    void* scratch[2];      // two H x W state images for the one-launch levels
+    hipStream_t side;      // own stream for the sums of f (default priority)
+    hipEvent_t ev_fork, ev_join;
+    void* prev;            // H x W state image (relErr(u) stop rule)
+    double* psums;         // patch partial sums, max over the levels that use them
+    double* cpend;         // corrections of the current level, max patches over coarse levels
+    double* fsum3;         // sums of f over the patches of side 3 and 7 (fused levels)
+    double* fsum7;
+    double* epart;         // energy partials
+    double* npart;         // norm partials (2 * NORM_BLOCKS)
+    double* dev3;          // energy, ||u - prev||^2, ||u||^2
+    double* host3;         // pinned copy of dev3
+    FbsGraph graphs[NGRAPHS];
+    int next_graph;
     std::string err;
 };
 
 namespace {
 
 thread_local std::string g_fbs_init_error;
+
+// Patches up to this side are summed by the colour kernel's own lane groups.
+constexpr int INLINE_SUM_MAX_SIDE = 15;
 
 mg_status ffail(mg_fbs_ctx* ctx, mg_status st, const char* fmt, ...)
 {
@@ -461,36 +711,37 @@ mg_status fcheck(mg_fbs_ctx* ctx, const void* u, const void* f)
 }
 
 template <typename T>
-hipError_t launch_pixel_level(const mg_fbs_ctx* c, const void* uin, void* uout, const void* f)
+hipError_t launch_pixel_level(const mg_fbs_ctx* c, hipStream_t st, const void* uin, void* uout, const void* f)
 {
     const int H = c->P.height, W = c->P.width;
-    dim3 grid((W + fbs::PT_W - 1) / fbs::PT_W, (H + fbs::PT_H - 1) / fbs::PT_H), block(256);
+    using Tile = fbs::PixelTile<T>;
+    dim3 grid((W + Tile::TW - 1) / Tile::TW, (H + Tile::TH - 1) / Tile::TH), block(Tile::NT);
     if (c->P.curvature == MG_CURV_MEAN)
-        hipLaunchKernelGGL((fbs::fbs_pixel_level_kernel<T, 0>), grid, block, 0, c->stream, (const T*)uin, (T*)uout,
-                           (const T*)f, H, W, c->P.alpha, c->P.steps);
+        hipLaunchKernelGGL((fbs::fbs_pixel_level_kernel<T, 0, Tile::TH, Tile::TW, Tile::NT>), grid, block, 0, st,
+                           (const T*)uin, (T*)uout, (const T*)f, H, W, c->P.alpha, c->P.steps);
     else
-        hipLaunchKernelGGL((fbs::fbs_pixel_level_kernel<T, 1>), grid, block, 0, c->stream, (const T*)uin, (T*)uout,
-                           (const T*)f, H, W, c->P.alpha, c->P.steps);
+        hipLaunchKernelGGL((fbs::fbs_pixel_level_kernel<T, 1, Tile::TH, Tile::TW, Tile::NT>), grid, block, 0, st,
+                           (const T*)uin, (T*)uout, (const T*)f, H, W, c->P.alpha, c->P.steps);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_pixel_colour(const mg_fbs_ctx* c, void* u, const void* f, int colour)
+hipError_t launch_pixel_colour(const mg_fbs_ctx* c, hipStream_t st, void* u, const void* f, int colour)
 {
     const int H = c->P.height, W = c->P.width;
     const size_t n = (size_t)((H - (colour >> 1) + 1) / 2) * ((W - (colour & 1) + 1) / 2);
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     if (c->P.curvature == MG_CURV_MEAN)
-        hipLaunchKernelGGL((fbs::fbs_pixel_colour_kernel<T, 0>), grid, block, 0, c->stream, (T*)u, (const T*)f, H, W,
+        hipLaunchKernelGGL((fbs::fbs_pixel_colour_kernel<T, 0>), grid, block, 0, st, (T*)u, (const T*)f, H, W,
                            colour, c->P.alpha, c->P.steps);
     else
-        hipLaunchKernelGGL((fbs::fbs_pixel_colour_kernel<T, 1>), grid, block, 0, c->stream, (T*)u, (const T*)f, H, W,
+        hipLaunchKernelGGL((fbs::fbs_pixel_colour_kernel<T, 1>), grid, block, 0, st, (T*)u, (const T*)f, H, W,
                            colour, c->P.alpha, c->P.steps);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sums(const mg_fbs_ctx* c, const void* u, const void* f, int b)
+hipError_t launch_sums(const mg_fbs_ctx* c, hipStream_t st, const void* u, const void* f, int b)
 {
     const int H = c->P.height, W = c->P.width;
     int mj, nj, nchunk, rows_per;
@@ -498,32 +749,33 @@ hipError_t launch_sums(const mg_fbs_ctx* c, const void* u, const void* f, int b)
     const int ngroups = mj * nj * nchunk;
     const long pix = (long)b * (b < rows_per ? b : rows_per);   // pixels per group
     auto grid_for = [&](int L) { return dim3((unsigned)(((size_t)ngroups * L + 255) / 256)); };
-#define FBS_SUMS(L)                                                                                                   \
-    hipLaunchKernelGGL((fbs::fbs_sums_kernel<T, L>), grid_for(L), dim3(256), 0, c->stream, (const T*)u, (const T*)f, \
-                       H, W, b, nj, ngroups, nchunk, rows_per, c->psums, c->cpend)
-    if (pix <= 16) FBS_SUMS(1);
-    else if (pix <= 128) FBS_SUMS(8);
-    else if (pix <= 1024) FBS_SUMS(64);
+#define FBS_SUMS(L)                                                                                                 \
+    hipLaunchKernelGGL((fbs::fbs_sums_kernel<T, L>), grid_for(L), dim3(256), 0, st, (const T*)u, (const T*)f, H, W, \
+                       b, nj, ngroups, nchunk, rows_per, c->psums)
+    if (pix <= 1024) FBS_SUMS(64);
     else FBS_SUMS(256);
 #undef FBS_SUMS
     return hipGetLastError();
 }
 
 template <typename T, int KIND>
-hipError_t launch_patch_kind(const mg_fbs_ctx* c, const void* u, int b, int colour)
+hipError_t launch_patch_kind(const mg_fbs_ctx* c, hipStream_t st, const void* u, const void* f, int b, int colour,
+                             int solved_from)
 {
     const int H = c->P.height, W = c->P.width;
     int mj, nj, nchunk, rows_per;
     fbs::patch_geometry(H, W, b, &mj, &nj, &nchunk, &rows_per);
+    if (b <= INLINE_SUM_MAX_SIDE) nchunk = 0;
     const int pr = colour >> 1, pc = colour & 1;
     const int npatch = ((mj - pr + 1) / 2) * ((nj - pc + 1) / 2);
     if (npatch <= 0) return hipSuccess;
     const int R = (b + 1) / 2;
     const int G = R < 64 ? R : 64;
     dim3 grid((unsigned)(((size_t)npatch * G + 255) / 256)), block(256);
-#define FBS_PATCH(GG)                                                                                                  \
-    hipLaunchKernelGGL((fbs::fbs_patch_kernel<T, KIND, GG>), grid, block, 0, c->stream, (const T*)u, H, W, b, mj, nj, \
-                       colour, nchunk, (const double*)c->psums, c->cpend, c->P.alpha, c->P.steps)
+#define FBS_PATCH(GG)                                                                                               \
+    hipLaunchKernelGGL((fbs::fbs_patch_kernel<T, KIND, GG>), grid, block, 0, st, (const T*)u, (const T*)f, H, W, b, \
+                       mj, nj, colour, solved_from, nchunk, (const double*)c->psums, c->cpend, c->P.alpha,           \
+                       c->P.steps)
     switch (G) {
     case 2: FBS_PATCH(2); break;
     case 4: FBS_PATCH(4); break;
@@ -537,94 +789,151 @@ hipError_t launch_patch_kind(const mg_fbs_ctx* c, const void* u, int b, int colo
 }
 
 template <typename T>
-hipError_t launch_patch(const mg_fbs_ctx* c, const void* u, int b, int colour)
+hipError_t launch_patch(const mg_fbs_ctx* c, hipStream_t st, const void* u, const void* f, int b, int colour,
+                        int solved_from)
 {
-    return c->P.curvature == MG_CURV_MEAN ? launch_patch_kind<T, 0>(c, u, b, colour)
-                                          : launch_patch_kind<T, 1>(c, u, b, colour);
+    return c->P.curvature == MG_CURV_MEAN ? launch_patch_kind<T, 0>(c, st, u, f, b, colour, solved_from)
+                                          : launch_patch_kind<T, 1>(c, st, u, f, b, colour, solved_from);
 }
 
 template <typename T>
-hipError_t launch_apply(const mg_fbs_ctx* c, const void* src, void* dst, int b)
+hipError_t launch_apply(const mg_fbs_ctx* c, hipStream_t st, const void* src, void* dst, int b, int cmin, int cmax)
 {
     const int H = c->P.height, W = c->P.width;
     const int nj = (W + b - 1) / b;
     const int gy = H < 1024 ? H : 1024;
     dim3 grid((W + 255) / 256, gy), block(256);
-    hipLaunchKernelGGL(fbs::fbs_apply_kernel<T>, grid, block, 0, c->stream, (const T*)src, (T*)dst, H, W, b, nj,
-                       (const double*)c->cpend, src == dst ? 1 : 0);
+    hipLaunchKernelGGL(fbs::fbs_apply_kernel<T>, grid, block, 0, st, (const T*)src, (T*)dst, H, W, b, nj,
+                       (const double*)c->cpend, src == dst ? 1 : 0, cmin, cmax);
     return hipGetLastError();
 }
 
-// Coarse level j >= 2 on the state in `src`; the result lands in `dst`.
+// Patch sides whose whole level runs as one fused launch, and its tile in patches.
+template <typename T, int KIND, int B, int TP>
+hipError_t launch_patch_level_kind(const mg_fbs_ctx* c, hipStream_t st, const void* src, void* dst)
+{
+    constexpr int NT = 256;
+    const int H = c->P.height, W = c->P.width;
+    const int mj = (H + B - 1) / B, nj = (W + B - 1) / B;
+    dim3 grid((nj + TP - 1) / TP, (mj + TP - 1) / TP), block(NT);
+    hipLaunchKernelGGL((fbs::fbs_patch_level_kernel<T, KIND, B, TP, NT>), grid, block, 0, st, (const T*)src, (T*)dst,
+                       (const double*)(B == 3 ? c->fsum3 : c->fsum7), H, W, mj, nj, c->P.alpha, c->P.steps);
+    return hipGetLastError();
+}
+
 template <typename T>
-mg_status coarse_level(mg_fbs_ctx* c, const void* src, void* dst, const void* f, int level, int only_colour)
+hipError_t launch_fsums(const mg_fbs_ctx* c, hipStream_t st, const void* f)
+{
+    const int H = c->P.height, W = c->P.width;
+    dim3 grid((W + 41) / 42, (H + 41) / 42), block(256);
+    hipLaunchKernelGGL(fbs::fbs_fsums_kernel<T>, grid, block, 0, st, (const T*)f, H, W, c->fsum3, c->fsum7);
+    return hipGetLastError();
+}
+
+bool has_fused_level(int b) { return b == 3 || b == 7; }
+
+template <typename T>
+hipError_t launch_patch_level(const mg_fbs_ctx* c, hipStream_t st, const void* src, void* dst, int b)
+{
+    const bool mc = c->P.curvature == MG_CURV_MEAN;
+    // tiles of (16 + 8) * 3 and (8 + 8) * 7 pixels square
+    constexpr int TP7 = 8;
+    if (b == 3) return mc ? launch_patch_level_kind<T, 0, 3, 16>(c, st, src, dst)
+                          : launch_patch_level_kind<T, 1, 3, 16>(c, st, src, dst);
+    return mc ? launch_patch_level_kind<T, 0, 7, TP7>(c, st, src, dst)
+              : launch_patch_level_kind<T, 1, 7, TP7>(c, st, src, dst);
+}
+
+// Coarse level j >= 2 on the state in `src`; the result lands in `dst`.
+// only_colour < 0 runs the four colours, else that colour alone.
+template <typename T>
+mg_status coarse_level(mg_fbs_ctx* c, hipStream_t st, const void* src, void* dst, const void* f, int level,
+                       int only_colour)
 {
     const int b = (1 << level) - 1;
-    hipError_t e = launch_sums<T>(c, src, f, b);
-    if (e != hipSuccess) return fhip(c, e, "patch sums launch");
-    for (int colour = 0; colour < 4; ++colour) {
-        if (only_colour >= 0 && colour != only_colour) continue;
-        e = launch_patch<T>(c, src, b, colour);
+    hipError_t e;
+    if (b > INLINE_SUM_MAX_SIDE && (e = launch_sums<T>(c, st, src, f, b)) != hipSuccess)
+        return fhip(c, e, "patch sums launch");
+    const int first = only_colour < 0 ? 0 : only_colour, last = only_colour < 0 ? 3 : only_colour;
+    for (int colour = first; colour <= last; ++colour) {
+        e = launch_patch<T>(c, st, src, f, b, colour, first);
         if (e != hipSuccess) return fhip(c, e, "patch colour launch");
     }
-    e = launch_apply<T>(c, src, dst, b);
+    e = launch_apply<T>(c, st, src, dst, b, first, last);
     if (e != hipSuccess) return fhip(c, e, "apply launch");
     return MG_OK;
 }
 
 // The levels of one V-cycle in order: 1..J, then J-1..1 for the full cycle.
+// Levels run as one launch (the pixel level and patch sides 3 and 7) read one
+// buffer and write another; the others may write in place.  Buffers are
+// assigned from the last level back so that the last level writes u: only a
+// lone one-launch level needs a final copy.  The sums of f for the one-launch
+// coarse levels are computed on the side stream, overlapping the levels before.
 template <typename T>
-mg_status run_levels(mg_fbs_ctx* c, void* u, const void* f, const int* levels, int nlevels)
+mg_status run_levels(mg_fbs_ctx* c, hipStream_t st, void* u, const void* f, const int* levels, int nlevels)
 {
-    void* cur = u;
+    auto one_launch = [&](int level) { return level == 1 || has_fused_level((1 << level) - 1); };
+    void* dst[64];
+    dst[nlevels - 1] = u;
+    for (int n = nlevels - 2; n >= 0; --n)
+        dst[n] = one_launch(levels[n + 1]) ? (dst[n + 1] == c->scratch[0] ? c->scratch[1] : c->scratch[0]) : dst[n + 1];
+    // the first level reads u; if it is a one-launch level it cannot also write u:
+    // then it writes scratch[0], and either the next level (which may write to
+    // another buffer) or a final copy brings the result to u
+    if (one_launch(levels[0]) && dst[0] == u) dst[0] = c->scratch[0];
+    bool need_fsums = false;
+    for (int n = 0; n < nlevels; ++n) need_fsums = need_fsums || (levels[n] > 1 && one_launch(levels[n]));
+    hipError_t e;
+    if (need_fsums) {
+        if ((e = hipEventRecord(c->ev_fork, st)) != hipSuccess) return fhip(c, e, "event record");
+        if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return fhip(c, e, "stream wait");
+        if ((e = launch_fsums<T>(c, c->side, f)) != hipSuccess) return fhip(c, e, "patch sums of f launch");
+        if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return fhip(c, e, "event record");
+    }
+    bool joined = false;
+    const void* cur = u;
     for (int n = 0; n < nlevels; ++n) {
         const int level = levels[n];
+        const int b = (1 << level) - 1;
         if (level == 1) {
-            void* other = cur == u ? c->ping : u;
-            hipError_t e = launch_pixel_level<T>(c, cur, other, f);
+            e = launch_pixel_level<T>(c, st, cur, dst[n], f);
             if (e != hipSuccess) return fhip(c, e, "pixel level launch");
-            cur = other;
+        } else if (has_fused_level(b)) {
+            if (!joined) {
+                if ((e = hipStreamWaitEvent(st, c->ev_join, 0)) != hipSuccess) return fhip(c, e, "stream wait");
+                joined = true;
+            }
+            e = launch_patch_level<T>(c, st, cur, dst[n], b);
+            if (e != hipSuccess) return fhip(c, e, "patch level launch");
         } else {
-            mg_status st = coarse_level<T>(c, cur, u, f, level, -1);
-            if (st != MG_OK) return st;
-            cur = u;
+            mg_status r = coarse_level<T>(c, st, cur, dst[n], f, level, -1);
+            if (r != MG_OK) return r;
         }
+        cur = dst[n];
     }
+    if (need_fsums && !joined && (e = hipStreamWaitEvent(st, c->ev_join, 0)) != hipSuccess)
+        return fhip(c, e, "stream wait");
     if (cur != u) {
-        hipError_t e = hipMemcpyAsync(u, cur, fbytes(c), hipMemcpyDeviceToDevice, c->stream);
+        e = hipMemcpyAsync(u, cur, fbytes(c), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return fhip(c, e, "state copy");
     }
     return MG_OK;
 }
 
-mg_status vcycle(mg_fbs_ctx* c, void* u, const void* f)
+mg_status vcycle_enqueue(mg_fbs_ctx* c, hipStream_t st, void* u, const void* f)
 {
     int lv[64], n = 0;
     for (int j = 1; j <= c->P.levels; ++j) lv[n++] = j;
     if (c->P.cycle == 1)
         for (int j = c->P.levels - 1; j >= 1; --j) lv[n++] = j;
-    return is64(c) ? run_levels<double>(c, u, f, lv, n) : run_levels<float>(c, u, f, lv, n);
+    return is64(c) ? run_levels<double>(c, st, u, f, lv, n) : run_levels<float>(c, st, u, f, lv, n);
 }
 
-mg_status level_only(mg_fbs_ctx* c, void* u, const void* f, int level)
-{
-    int lv[1] = {level};
-    return is64(c) ? run_levels<double>(c, u, f, lv, 1) : run_levels<float>(c, u, f, lv, 1);
-}
-
-mg_status sweep_only(mg_fbs_ctx* c, void* u, const void* f, int level, int colour)
-{
-    if (level == 1) {
-        hipError_t e = is64(c) ? launch_pixel_colour<double>(c, u, f, colour) : launch_pixel_colour<float>(c, u, f, colour);
-        return e == hipSuccess ? MG_OK : fhip(c, e, "pixel colour launch");
-    }
-    return is64(c) ? coarse_level<double>(c, u, u, f, level, colour) : coarse_level<float>(c, u, u, f, level, colour);
-}
-
-mgc::LaunchCtx energy_ctx(const mg_fbs_ctx* c)
+mgc::LaunchCtx energy_ctx(const mg_fbs_ctx* c, hipStream_t st)
 {
     mgc::LaunchCtx L;
-    L.stream = c->stream;
+    L.stream = st;
     L.H = c->P.height;
     L.W = c->P.width;
     L.alpha = c->P.alpha;
@@ -635,29 +944,95 @@ mgc::LaunchCtx energy_ctx(const mg_fbs_ctx* c)
     return L;
 }
 
-// Enqueue F(u) into dev3[0] and, if `norms`, ||u - prev||^2 and ||u||^2 into
-// dev3[1..2]; copy to the pinned host mirror and wait.
-mg_status measure(mg_fbs_ctx* c, const void* u, const void* f, bool norms)
+// F(u) into dev3[0] and, if `norms`, ||u - prev||^2 and ||u||^2 into
+// dev3[1..2], then a copy to the pinned host mirror (enqueued only).
+mg_status measure_enqueue(mg_fbs_ctx* c, hipStream_t st, const void* u, const void* f, bool norms)
 {
-    hipError_t e = mgc::launch_energy(energy_ctx(c), u, f, c->epart, c->dev3);
+    hipError_t e = mgc::launch_energy(energy_ctx(c, st), u, f, c->epart, c->dev3);
     if (e != hipSuccess) return fhip(c, e, "energy launch");
     if (norms) {
         const size_t n = (size_t)c->P.height * c->P.width;
         if (is64(c))
-            hipLaunchKernelGGL(fbs::fbs_norms_kernel<double>, dim3(fbs::NORM_BLOCKS), dim3(256), 0, c->stream,
+            hipLaunchKernelGGL(fbs::fbs_norms_kernel<double>, dim3(fbs::NORM_BLOCKS), dim3(256), 0, st,
                                (const double*)u, (const double*)c->prev, n, c->npart);
         else
-            hipLaunchKernelGGL(fbs::fbs_norms_kernel<float>, dim3(fbs::NORM_BLOCKS), dim3(256), 0, c->stream,
+            hipLaunchKernelGGL(fbs::fbs_norms_kernel<float>, dim3(fbs::NORM_BLOCKS), dim3(256), 0, st,
                                (const float*)u, (const float*)c->prev, n, c->npart);
-        hipLaunchKernelGGL(fbs::fbs_norms_final_kernel, dim3(1), dim3(256), 0, c->stream, (const double*)c->npart,
+        hipLaunchKernelGGL(fbs::fbs_norms_final_kernel, dim3(1), dim3(256), 0, st, (const double*)c->npart,
                            fbs::NORM_BLOCKS, c->dev3 + 1);
         if ((e = hipGetLastError()) != hipSuccess) return fhip(c, e, "norm launch");
     }
-    e = hipMemcpyAsync(c->host3, c->dev3, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(c->host3, c->dev3, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return fhip(c, e, "result copy");
-    e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return fhip(c, e, "stream synchronize");
     return MG_OK;
+}
+
+void drop_graph(FbsGraph& g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = FbsGraph();
+}
+
+// The captured graph for (u, f, what), capturing it on the own stream first if needed.
+mg_status get_graph(mg_fbs_ctx* c, void* u, const void* f, int what, hipGraphExec_t* out)
+{
+    for (auto& g : c->graphs)
+        if (g.exec && g.u == u && g.f == f && g.what == what) {
+            *out = g.exec;
+            return MG_OK;
+        }
+    FbsGraph& g = c->graphs[c->next_graph];
+    c->next_graph = (c->next_graph + 1) % NGRAPHS;
+    drop_graph(g);
+    hipStream_t st = c->gstream;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fhip(c, e, "begin capture");
+    mg_status r = MG_OK;
+    if (what == 2) {
+        e = hipMemcpyAsync(c->prev, u, fbytes(c), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) r = fhip(c, e, "state copy");
+    }
+    if (r == MG_OK) r = vcycle_enqueue(c, st, u, f);
+    if (r == MG_OK && what >= 1) r = measure_enqueue(c, st, u, f, what == 2);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (r != MG_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess) return fhip(c, e, "end capture");
+    g.graph = graph;
+    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) {
+        drop_graph(g);
+        return fhip(c, e, "graph instantiate");
+    }
+    g.u = u;
+    g.f = f;
+    g.what = what;
+    *out = g.exec;
+    return MG_OK;
+}
+
+// Launch graph `what` for (u, f) into the caller's stream (captured once on the
+// own stream); wait: also block until it is done.
+mg_status replay(mg_fbs_ctx* c, void* u, const void* f, int what, bool wait)
+{
+    hipGraphExec_t exec;
+    mg_status r = get_graph(c, u, f, what, &exec);
+    if (r != MG_OK) return r;
+    hipError_t e;
+    if ((e = hipGraphLaunch(exec, c->stream)) != hipSuccess) return fhip(c, e, "graph launch");
+    if (wait && (e = hipStreamSynchronize(c->stream)) != hipSuccess) return fhip(c, e, "stream synchronize");
+    return MG_OK;
+}
+
+mg_status measure_now(mg_fbs_ctx* c, const void* u, const void* f)
+{
+    mg_status r = measure_enqueue(c, c->stream, u, f, false);
+    if (r != MG_OK) return r;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? MG_OK : fhip(c, e, "stream synchronize");
 }
 
 }  // namespace
@@ -701,8 +1076,13 @@ mg_status mg_fbs_init(const mg_fbs_params* params, void* hip_stream, mg_fbs_ctx*
     if (!c) return ffail(nullptr, MG_E_NOMEM, "host allocation failed");
     c->P = p;
     c->stream = (hipStream_t)hip_stream;
-    c->ping = c->prev = nullptr;
+    c->gstream = nullptr;
+    c->scratch[0] = c->scratch[1] = c->prev = nullptr;
+    c->side = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
     c->psums = c->cpend = c->epart = c->npart = c->dev3 = c->host3 = nullptr;
+    c->fsum3 = c->fsum7 = nullptr;
+    c->next_graph = 0;
     (void)hipGetDevice(&c->device);
     size_t n_ps = 1, n_cp = 1;
     for (int level = 2; level <= p.levels; ++level) {
@@ -713,9 +1093,12 @@ mg_status mg_fbs_init(const mg_fbs_params* params, void* hip_stream, mg_fbs_ctx*
     }
     const size_t nb = fbytes(c);
     const int ne = mgc::energy_partials_count(p.height, p.width);
-    if (hipMalloc(&c->ping, nb) != hipSuccess || hipMalloc(&c->prev, nb) != hipSuccess ||
+    if (hipMalloc(&c->scratch[0], nb) != hipSuccess || hipMalloc(&c->scratch[1], nb) != hipSuccess ||
+        hipMalloc(&c->prev, nb) != hipSuccess ||
         hipMalloc((void**)&c->psums, sizeof(double) * n_ps) != hipSuccess ||
         hipMalloc((void**)&c->cpend, sizeof(double) * n_cp) != hipSuccess ||
+        hipMalloc((void**)&c->fsum3, sizeof(double) * ((p.height + 2) / 3) * ((p.width + 2) / 3)) != hipSuccess ||
+        hipMalloc((void**)&c->fsum7, sizeof(double) * ((p.height + 6) / 7) * ((p.width + 6) / 7)) != hipSuccess ||
         hipMalloc((void**)&c->epart, sizeof(double) * ne) != hipSuccess ||
         hipMalloc((void**)&c->npart, sizeof(double) * 2 * fbs::NORM_BLOCKS) != hipSuccess ||
         hipMalloc((void**)&c->dev3, 3 * sizeof(double)) != hipSuccess ||
@@ -723,6 +1106,14 @@ mg_status mg_fbs_init(const mg_fbs_params* params, void* hip_stream, mg_fbs_ctx*
         mg_fbs_destroy(c);
         (void)hipGetLastError();
         return ffail(nullptr, MG_E_NOMEM, "device allocation of 2 x %zu bytes failed", nb);
+    }
+    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        mg_fbs_destroy(c);
+        (void)hipGetLastError();
+        return ffail(nullptr, MG_E_DEVICE, "stream or event creation failed");
     }
     *out = c;
     return MG_OK;
@@ -732,9 +1123,8 @@ mg_status mg_fbs_vcycle(mg_fbs_ctx* ctx, void* u, const void* f, double* energy_
 {
     mg_status st = fcheck(ctx, u, f);
     if (st != MG_OK) return st;
-    if ((st = vcycle(ctx, u, f)) != MG_OK || !energy_after) return st;
-    if ((st = measure(ctx, u, f, false)) != MG_OK) return st;
-    *energy_after = ctx->host3[0];
+    if ((st = replay(ctx, u, f, energy_after ? 1 : 0, energy_after != nullptr)) != MG_OK) return st;
+    if (energy_after) *energy_after = ctx->host3[0];
     return MG_OK;
 }
 
@@ -743,7 +1133,9 @@ mg_status mg_fbs_level(mg_fbs_ctx* ctx, void* u, const void* f, int32_t level)
     mg_status st = fcheck(ctx, u, f);
     if (st != MG_OK) return st;
     if (level < 1 || level > ctx->P.levels) return ffail(ctx, MG_E_INVALID, "level must be in [1, %d]", ctx->P.levels);
-    return level_only(ctx, u, f, level);
+    int lv[1] = {level};
+    return is64(ctx) ? run_levels<double>(ctx, ctx->stream, u, f, lv, 1)
+                     : run_levels<float>(ctx, ctx->stream, u, f, lv, 1);
 }
 
 mg_status mg_fbs_sweep(mg_fbs_ctx* ctx, void* u, const void* f, int32_t level, int32_t colour)
@@ -752,7 +1144,13 @@ mg_status mg_fbs_sweep(mg_fbs_ctx* ctx, void* u, const void* f, int32_t level, i
     if (st != MG_OK) return st;
     if (level < 1 || level > ctx->P.levels) return ffail(ctx, MG_E_INVALID, "level must be in [1, %d]", ctx->P.levels);
     if (colour < 0 || colour > 3) return ffail(ctx, MG_E_INVALID, "colour must be in [0, 4)");
-    return sweep_only(ctx, u, f, level, colour);
+    if (level == 1) {
+        hipError_t e = is64(ctx) ? launch_pixel_colour<double>(ctx, ctx->stream, u, f, colour)
+                                 : launch_pixel_colour<float>(ctx, ctx->stream, u, f, colour);
+        return e == hipSuccess ? MG_OK : fhip(ctx, e, "pixel colour launch");
+    }
+    return is64(ctx) ? coarse_level<double>(ctx, ctx->stream, u, u, f, level, colour)
+                     : coarse_level<float>(ctx, ctx->stream, u, u, f, level, colour);
 }
 
 mg_status mg_fbs_energy(mg_fbs_ctx* ctx, const void* u, const void* f, double* energy)
@@ -760,7 +1158,7 @@ mg_status mg_fbs_energy(mg_fbs_ctx* ctx, const void* u, const void* f, double* e
     mg_status st = fcheck(ctx, u, f);
     if (st != MG_OK) return st;
     if (!energy) return ffail(ctx, MG_E_INVALID, "energy output must be non-null");
-    if ((st = measure(ctx, u, f, false)) != MG_OK) return st;
+    if ((st = measure_now(ctx, u, f)) != MG_OK) return st;
     *energy = ctx->host3[0];
     return MG_OK;
 }
@@ -773,7 +1171,7 @@ mg_status mg_fbs_solve(mg_fbs_ctx* ctx, void* u, const void* f, double tol, int3
     if (max_vcycles < 0) return ffail(ctx, MG_E_INVALID, "max_vcycles must be >= 0");
     if (!std::isfinite(tol)) return ffail(ctx, MG_E_INVALID, "tol must be finite");
     if (stop != MG_STOP_ENERGY && stop != MG_STOP_RELERR_U) return ffail(ctx, MG_E_INVALID, "stop must be MG_STOP_ENERGY or MG_STOP_RELERR_U");
-    if ((st = measure(ctx, u, f, false)) != MG_OK) return st;
+    if ((st = measure_now(ctx, u, f)) != MG_OK) return st;
     double e_prev = ctx->host3[0];
     if (!std::isfinite(e_prev)) return ffail(ctx, MG_E_NONFINITE, "energy of the initial state is not finite");
     if (energy_trace) energy_trace[0] = e_prev;
@@ -782,12 +1180,7 @@ mg_status mg_fbs_solve(mg_fbs_ctx* ctx, void* u, const void* f, double tol, int3
     double e = e_prev;
     const bool relerr = stop == MG_STOP_RELERR_U;
     while (done < max_vcycles) {
-        if (relerr) {
-            hipError_t he = hipMemcpyAsync(ctx->prev, u, fbytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
-            if (he != hipSuccess) return fhip(ctx, he, "state copy");
-        }
-        if ((st = vcycle(ctx, u, f)) != MG_OK) return st;
-        if ((st = measure(ctx, u, f, relerr)) != MG_OK) return st;
+        if ((st = replay(ctx, u, f, relerr ? 2 : 1, true)) != MG_OK) return st;
         ++done;
         e = ctx->host3[0];
         if (energy_trace) energy_trace[done] = e;
@@ -808,10 +1201,20 @@ void mg_fbs_destroy(mg_fbs_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->ping) (void)hipFree(ctx->ping);
+    if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    for (auto& g : ctx->graphs) drop_graph(g);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->scratch[0]) (void)hipFree(ctx->scratch[0]);
+    if (ctx->scratch[1]) (void)hipFree(ctx->scratch[1]);
     if (ctx->prev) (void)hipFree(ctx->prev);
     if (ctx->psums) (void)hipFree(ctx->psums);
     if (ctx->cpend) (void)hipFree(ctx->cpend);
+    if (ctx->fsum3) (void)hipFree(ctx->fsum3);
+    if (ctx->fsum7) (void)hipFree(ctx->fsum7);
     if (ctx->epart) (void)hipFree(ctx->epart);
     if (ctx->npart) (void)hipFree(ctx->npart);
     if (ctx->dev3) (void)hipFree(ctx->dev3);

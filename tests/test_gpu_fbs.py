@@ -209,3 +209,29 @@ def test_fixed_point_and_errors(mg):
         s.sweep(ud, gd, 1, 4)
     with pytest.raises(mg.MgCurvError):
         s.vcycle(ud, ud)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_graph_replays_match_eager_levels(mg, kind):
+    """mg_fbs_vcycle replays a captured graph; every replay must equal the same V-cycle run
+    eagerly level by level, with other eager work and synchronisations in between, and a
+    second buffer pair (another captured graph) must not disturb the first."""
+    h, w = 130, 150
+    alpha, scale = REGIMES[1]
+    f, _ = _inputs(h, w, 71, scale, torch.float32)
+    s = mg.FbsSolver(h, w, alpha, kind, levels=4, dtype=torch.float32, cycle=1, steps=2)
+    fd = dev(f, torch.float32)
+    ug, ue, u2 = dev(f, torch.float32), dev(f, torch.float32), dev(f, torch.float32)
+    order = [1, 2, 3, 4, 3, 2, 1]
+    _case(f"fbs graph replay kind={kind}")
+    for rep in range(4):
+        s.vcycle(ug, fd)
+        for level in order:
+            s.level(ue, fd, level)
+        e_eager = s.energy(ue, fd)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ug), host(ue)), f"replay {rep}"
+        assert s.energy(ug, fd) == e_eager
+        if rep == 1:
+            e2 = s.vcycle(u2, fd, want_energy=True)
+            assert e2 == s.energy(u2, fd)
