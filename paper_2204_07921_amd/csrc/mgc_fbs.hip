@@ -123,59 +123,66 @@ __device__ __forceinline__ constexpr int ring_dj(int k)
     return k < 2 ? (k == 0 ? -1 : 1) : (k < 4 ? 0 : (k == 4 ? -1 : (k == 5 ? 1 : (k == 6 ? 1 : -1))));
 }
 
-// Visit an nr x nc region: a wave covers 64 consecutive columns of a row (the
-// accesses coalesce), NT / 64 rows per pass, K rows' loads in flight per thread
-// before the first store; no integer division.
-template <int NT, int K, class Ld, class St>
-__device__ __forceinline__ void copy2d(int nr, int nc, const Ld& ld, const St& st)
+// Row-major positions (a, b) in a grid with nb columns of the elements t0,
+// t0 + S, t0 + 2 S, ...: one division at the start, then a fixed step with a
+// carry (the index arithmetic of strided loops otherwise dominates these
+// kernels' instruction counts).
+struct GridWalk {
+    int a, b, da, db, nb;
+    __device__ __forceinline__ GridWalk(int t0, int S, int nb_) : nb(nb_)
+    {
+        a = t0 / nb;
+        b = t0 - a * nb;
+        da = S / nb;
+        db = S - da * nb;
+    }
+    __device__ __forceinline__ bool next()
+    {
+        a += da;
+        b += db;
+        const bool carry = b >= nb;
+        if (carry) {
+            b -= nb;
+            ++a;
+        }
+        return carry;
+    }
+};
+
+// dst[r * dstride + c] = src[r * sstride + c] for an nr x nc region, thread t
+// taking the elements t, t + NT, ... in row-major order with K loads in flight
+// before the first store; offsets advance by a fixed step.
+template <int NT, int K, class T, class SS, class DS>
+__device__ __forceinline__ void tile_copy(int nr, int nc, const T* __restrict__ src, SS sstride, T* __restrict__ dst,
+                                          DS dstride)
 {
-    constexpr int RS = NT / 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int c = tx; c < nc; c += 64) {
-        for (int r0 = ty; r0 < nr; r0 += RS * K) {
-            decltype(ld(0, 0)) tmp[K];
+    if (nr <= 0 || nc <= 0) return;
+    const int n = nr * nc;
+    GridWalk w(threadIdx.x, NT, nc);
+    SS so = (SS)w.a * sstride + w.b;
+    DS dof = (DS)w.a * dstride + w.b;
+    const SS sstep = (SS)w.da * sstride + w.db, scarry = sstride - nc;
+    const DS dstep = (DS)w.da * dstride + w.db, dcarry = dstride - nc;
+    for (int base = threadIdx.x; base < n; base += NT * K) {
+        T tmp[K];
+        {
+            GridWalk v = w;
+            SS o = so;
 #pragma unroll
             for (int m = 0; m < K; ++m) {
-                const int r = r0 + m * RS;
-                if (r < nr) tmp[m] = ld(r, c);
-            }
-#pragma unroll
-            for (int m = 0; m < K; ++m) {
-                const int r = r0 + m * RS;
-                if (r < nr) st(r, c, tmp[m]);
+                if (base + m * NT < n) tmp[m] = src[o];
+                o += sstep;
+                if (v.next()) o += scarry;
             }
         }
-    }
-}
-
-// Copy an nr x nc region of u and of f into two LDS tiles with the mapping of
-// copy2d, the loads of K rows of both arrays in flight per thread.
-template <int NT, int K, class T, class Idx>
-__device__ __forceinline__ void copy_pair(int nr, int nc, const T* __restrict__ u, const T* __restrict__ f, int W,
-                                          int r_img, int c_img, T* su, T* sf, const Idx& lds_index)
-{
-    constexpr int RS = NT / 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int c = tx; c < nc; c += 64) {
-        for (int r0 = ty; r0 < nr; r0 += RS * K) {
-            T a[K], b[K];
 #pragma unroll
-            for (int m = 0; m < K; ++m) {
-                const int r = r0 + m * RS;
-                if (r < nr) {
-                    const size_t g = (size_t)(r_img + r) * W + (c_img + c);
-                    a[m] = u[g];
-                    b[m] = f[g];
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < K; ++m) {
-                const int r = r0 + m * RS;
-                if (r < nr) {
-                    const int l = lds_index(r, c);
-                    su[l] = a[m];
-                    sf[l] = b[m];
-                }
+        for (int m = 0; m < K; ++m) {
+            if (base + m * NT < n) dst[dof] = tmp[m];
+            so += sstep;
+            dof += dstep;
+            if (w.next()) {
+                so += scarry;
+                dof += dcarry;
             }
         }
     }
@@ -229,8 +236,8 @@ __global__ __launch_bounds__(NT) void fbs_pixel_level_kernel(const T* __restrict
     const int c_lo = max(0, lx), c_hi = min(W, x0 + TW + PHALO);
     const int nr = r_hi - r_lo, nc = c_hi - c_lo;
     // u and f of the loaded region (f is read by the pixels solved, all inside it)
-    copy_pair<NT, 4>(nr, nc, uin, f, W, r_lo, c_lo, su, sf,
-                      [&](int r, int c) { return (r_lo + r - ly) * LW + (c_lo + c - lx); });
+    tile_copy<NT, 12>(nr, nc, uin + (size_t)r_lo * W + c_lo, (long)W, su + (r_lo - ly) * LW + (c_lo - lx), LW);
+    tile_copy<NT, 12>(nr, nc, f + (size_t)r_lo * W + c_lo, (long)W, sf + (r_lo - ly) * LW + (c_lo - lx), LW);
     __syncthreads();
     auto at = [&](int ii, int jj) { return (double)su[(ii - ly) * LW + (jj - lx)]; };
     for (int k = 0; k < 4; ++k) {
@@ -239,8 +246,9 @@ __global__ __launch_bounds__(NT) void fbs_pixel_level_kernel(const T* __restrict
         const int vc0 = c_lo == 0 ? 0 : c_lo + k + 1, vc1 = c_hi == W ? W : c_hi - k - 1;
         const int i0 = vr0 + ((vr0 & 1) != (k >> 1)), j0 = vc0 + ((vc0 & 1) != (k & 1));
         const int ni = i0 < vr1 ? (vr1 - i0 + 1) / 2 : 0, nj = j0 < vc1 ? (vc1 - j0 + 1) / 2 : 0;
-        for (int t = threadIdx.x; t < ni * nj; t += NT) {
-            const int i = i0 + 2 * (t / nj), j = j0 + 2 * (t % nj);
+        if (ni > 0 && nj > 0)
+        for (GridWalk w(threadIdx.x, NT, nj); w.a < ni; w.next()) {
+            const int i = i0 + 2 * w.a, j = j0 + 2 * w.b;
             const double uo = at(i, j);
             const double fs = (double)sf[(i - ly) * LW + (j - lx)] - uo;
             const double c = pixel_correction<KIND>(at, i, j, H, W, fs, alpha, steps);
@@ -250,8 +258,7 @@ __global__ __launch_bounds__(NT) void fbs_pixel_level_kernel(const T* __restrict
         __syncthreads();
     }
     const int onr = min(H, y0 + TH) - y0, onc = min(W, x0 + TW) - x0;
-    copy2d<NT, 4>(onr, onc, [&](int r, int c) { return su[(y0 + r - ly) * LW + (x0 + c - lx)]; },
-                  [&](int r, int c, T x) { uout[(size_t)(y0 + r) * W + (x0 + c)] = x; });
+    tile_copy<NT, 8>(onr, onc, su + (y0 - ly) * LW + (x0 - lx), LW, uout + (size_t)y0 * W + x0, (long)W);
 }
 
 // Tile of the pixel level per state type: (rows, columns, threads).
@@ -301,8 +308,7 @@ __global__ __launch_bounds__(NT) void fbs_patch_level_kernel(const T* __restrict
     const int qa = max(0, lq0), qb = min(nj, Q0 + TP + HALO);
     const int ly = lp0 * B, lx = lq0 * B;
     const int ra = pa * B, rb = min(H, pb * B), ca = qa * B, cb = min(W, qb * B);
-    copy2d<NT, 4>(rb - ra, cb - ca, [&](int r, int c) { return uin[(size_t)(ra + r) * W + (ca + c)]; },
-                  [&](int r, int c, T x) { su[(ra + r - ly) * LPX + (ca + c - lx)] = x; });
+    tile_copy<NT, 16>(rb - ra, cb - ca, uin + (size_t)ra * W + ca, (long)W, su + (ra - ly) * LPX + (ca - lx), LPX);
     for (int t = threadIdx.x; t < LP * LP; t += NT) sc[t] = 0.0;
     __syncthreads();
     // sum of f - u over each patch as (sum of f) - (sum of u): the sums of f come
@@ -322,8 +328,9 @@ __global__ __launch_bounds__(NT) void fbs_patch_level_kernel(const T* __restrict
         const int vq0 = qa == 0 ? 0 : qa + k + 1, vq1 = qb == nj ? nj : qb - k - 1;
         const int p0 = vp0 + ((vp0 & 1) != (k >> 1)), q0 = vq0 + ((vq0 & 1) != (k & 1));
         const int np = p0 < vp1 ? (vp1 - p0 + 1) / 2 : 0, nq = q0 < vq1 ? (vq1 - q0 + 1) / 2 : 0;
-        for (int g = threadIdx.x / G; g < np * nq; g += NT / G) {
-            const int p = p0 + 2 * (g / nq), q = q0 + 2 * (g % nq);
+        if (np > 0 && nq > 0)
+        for (GridWalk w(threadIdx.x / G, NT / G, nq); w.a < np; w.next()) {
+            const int p = p0 + 2 * w.a, q = q0 + 2 * w.b;
             const int r0 = p * B, r1 = min(r0 + B, H), c0 = q * B, c1 = min(c0 + B, W);
             const double s = (double)((r1 - r0) * (c1 - c0)), fs = ss[(p - lp0) * LP + (q - lq0)] / s;
             const int oi = r0 + R - 1, oj = c0 + R - 1;
@@ -380,16 +387,20 @@ __global__ __launch_bounds__(NT) void fbs_patch_level_kernel(const T* __restrict
         }
         __syncthreads();
     }
-    const int o_r0 = P0 * B, o_c0 = Q0 * B;
-    const int onr = min(H, (P0 + TP) * B) - o_r0, onc = min(W, (Q0 + TP) * B) - o_c0;
-    copy2d<NT, 4>(onr, onc,
-                  [&](int r, int cc) {
-                      const int i = o_r0 + r, j = o_c0 + cc;
-                      const T x = su[(i - ly) * LPX + (j - lx)];
-                      const double c = sc[(i / B - lp0) * LP + (j / B - lq0)];
-                      return c != 0.0 ? (T)((double)x + c) : x;
-                  },
-                  [&](int r, int cc, T x) { uout[(size_t)(o_r0 + r) * W + (o_c0 + cc)] = x; });
+    // owned pixels with their patch's correction: one row segment of a patch per step
+    const int o_r0 = P0 * B, onr = min(H, (P0 + TP) * B) - o_r0, ntq = min(nj, Q0 + TP) - Q0;
+    if (onr > 0 && ntq > 0)
+        for (GridWalk w(threadIdx.x, NT, ntq); w.a < onr; w.next()) {
+            const int i = o_r0 + w.a, q = Q0 + w.b;
+            const double c = sc[(i / B - lp0) * LP + (q - lq0)];
+            const T* srow = su + (i - ly) * LPX - lx;
+            T* drow = uout + (size_t)i * W;
+#pragma unroll
+            for (int m = 0; m < B; ++m) {
+                const int j = q * B + m;
+                if (j < W) drow[j] = c != 0.0 ? (T)((double)srow[j] + c) : srow[j];
+            }
+        }
 }
 
 // Sums of f over the patches of side 3 and of side 7 (row-major within a patch):
@@ -402,8 +413,7 @@ __global__ __launch_bounds__(256) void fbs_fsums_kernel(const T* __restrict__ f,
     __shared__ T sf[TS * TS];
     const int y0 = blockIdx.y * TS, x0 = blockIdx.x * TS;
     const int nr = min(TS, H - y0), nc = min(TS, W - x0);
-    copy2d<256, 4>(nr, nc, [&](int r, int c) { return f[(size_t)(y0 + r) * W + (x0 + c)]; },
-                   [&](int r, int c, T x) { sf[r * TS + c] = x; });
+    tile_copy<256, 7>(nr, nc, f + (size_t)y0 * W + x0, (long)W, sf, TS);
     __syncthreads();
     const int n3 = (W + 2) / 3, n7 = (W + 6) / 7;
     for (int t = threadIdx.x; t < 14 * 14 + 6 * 6; t += 256) {
@@ -657,8 +667,6 @@ struct mg_fbs_ctx {
     hipStream_t stream;    // caller's stream: every launch and graph replay goes here
     hipStream_t gstream;   // own stream, used only to capture graphs (default priority)
     void* scratch[2];      // two H x W state images for the one-launch levels
-    hipStream_t side;      // own stream for the sums of f (default priority)
-    hipEvent_t ev_fork, ev_join;
     void* prev;            // H x W state image (relErr(u) stop rule)
     double* psums;         // patch partial sums, max over the levels that use them
     double* cpend;         // corrections of the current level, max patches over coarse levels
@@ -869,7 +877,8 @@ mg_status coarse_level(mg_fbs_ctx* c, hipStream_t st, const void* src, void* dst
 // buffer and write another; the others may write in place.  Buffers are
 // assigned from the last level back so that the last level writes u: only a
 // lone one-launch level needs a final copy.  The sums of f for the one-launch
-// coarse levels are computed on the side stream, overlapping the levels before.
+// coarse levels are computed first, in the same stream (a forked branch costs
+// more in cross-queue waits than it overlaps).
 template <typename T>
 mg_status run_levels(mg_fbs_ctx* c, hipStream_t st, void* u, const void* f, const int* levels, int nlevels)
 {
@@ -885,13 +894,7 @@ mg_status run_levels(mg_fbs_ctx* c, hipStream_t st, void* u, const void* f, cons
     bool need_fsums = false;
     for (int n = 0; n < nlevels; ++n) need_fsums = need_fsums || (levels[n] > 1 && one_launch(levels[n]));
     hipError_t e;
-    if (need_fsums) {
-        if ((e = hipEventRecord(c->ev_fork, st)) != hipSuccess) return fhip(c, e, "event record");
-        if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return fhip(c, e, "stream wait");
-        if ((e = launch_fsums<T>(c, c->side, f)) != hipSuccess) return fhip(c, e, "patch sums of f launch");
-        if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return fhip(c, e, "event record");
-    }
-    bool joined = false;
+    if (need_fsums && (e = launch_fsums<T>(c, st, f)) != hipSuccess) return fhip(c, e, "patch sums of f launch");
     const void* cur = u;
     for (int n = 0; n < nlevels; ++n) {
         const int level = levels[n];
@@ -900,10 +903,6 @@ mg_status run_levels(mg_fbs_ctx* c, hipStream_t st, void* u, const void* f, cons
             e = launch_pixel_level<T>(c, st, cur, dst[n], f);
             if (e != hipSuccess) return fhip(c, e, "pixel level launch");
         } else if (has_fused_level(b)) {
-            if (!joined) {
-                if ((e = hipStreamWaitEvent(st, c->ev_join, 0)) != hipSuccess) return fhip(c, e, "stream wait");
-                joined = true;
-            }
             e = launch_patch_level<T>(c, st, cur, dst[n], b);
             if (e != hipSuccess) return fhip(c, e, "patch level launch");
         } else {
@@ -912,8 +911,6 @@ mg_status run_levels(mg_fbs_ctx* c, hipStream_t st, void* u, const void* f, cons
         }
         cur = dst[n];
     }
-    if (need_fsums && !joined && (e = hipStreamWaitEvent(st, c->ev_join, 0)) != hipSuccess)
-        return fhip(c, e, "stream wait");
     if (cur != u) {
         e = hipMemcpyAsync(u, cur, fbytes(c), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return fhip(c, e, "state copy");
@@ -1078,8 +1075,6 @@ mg_status mg_fbs_init(const mg_fbs_params* params, void* hip_stream, mg_fbs_ctx*
     c->stream = (hipStream_t)hip_stream;
     c->gstream = nullptr;
     c->scratch[0] = c->scratch[1] = c->prev = nullptr;
-    c->side = nullptr;
-    c->ev_fork = c->ev_join = nullptr;
     c->psums = c->cpend = c->epart = c->npart = c->dev3 = c->host3 = nullptr;
     c->fsum3 = c->fsum7 = nullptr;
     c->next_graph = 0;
@@ -1107,13 +1102,10 @@ mg_status mg_fbs_init(const mg_fbs_params* params, void* hip_stream, mg_fbs_ctx*
         (void)hipGetLastError();
         return ffail(nullptr, MG_E_NOMEM, "device allocation of 2 x %zu bytes failed", nb);
     }
-    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
         mg_fbs_destroy(c);
         (void)hipGetLastError();
-        return ffail(nullptr, MG_E_DEVICE, "stream or event creation failed");
+        return ffail(nullptr, MG_E_DEVICE, "stream creation failed");
     }
     *out = c;
     return MG_OK;
@@ -1202,12 +1194,9 @@ void mg_fbs_destroy(mg_fbs_ctx* ctx)
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
-    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     for (auto& g : ctx->graphs) drop_graph(g);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
-    if (ctx->side) (void)hipStreamDestroy(ctx->side);
-    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+
     if (ctx->scratch[0]) (void)hipFree(ctx->scratch[0]);
     if (ctx->scratch[1]) (void)hipFree(ctx->scratch[1]);
     if (ctx->prev) (void)hipFree(ctx->prev);
