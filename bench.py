@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--batch-solve", action="store_true", help="also solve all 256 images to 1e-6")
     ap.add_argument("--no-warm", action="store_true", help="skip the CNN warm-start comparison")
     ap.add_argument("--no-fbs", action="store_true", help="skip the paper's own local step (FBS) measurement")
+    ap.add_argument("--fbs-only", action="store_true",
+                    help="run only the FBS measurement and print its JSON (for profiling its kernels)")
     ap.add_argument("--warm-batch", type=int, default=0,
                     help="also compare plain and warm-started batched solves on this many 1024x1024 images")
     return ap.parse_args()
@@ -245,6 +247,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only (the path has no multi-GPU "
                           "sharding)", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.fbs_only:
+        print(json.dumps({"fbs": fbs_measure(args.steps, args.warmup)}), flush=True)
+        return
     import torch
     from paper_2204_07921_amd import mgcurv
     from synth import noisy_image
