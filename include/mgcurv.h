@@ -328,6 +328,61 @@ void mg_fbs_destroy(mg_fbs_ctx *ctx);
 /* Last error of ctx, or of this thread's last failed mg_fbs_init (ctx NULL). */
 const char *mg_fbs_last_error(const mg_fbs_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Reconstruction (Section 5): recover u from b = A u + noise by minimising
+ *     1/2 ||A u - b||^2 + alpha sum |H(u)|          (H: mean curvature, as above).
+ * A is a 5 x 5 Gaussian blur of width blur_sigma, normalised, positions outside
+ * the image contributing nothing (the paper's Radon and Fourier operators need
+ * data this library does not have; the blur is the operator this path is built
+ * and measured with).  Patches of side 2^j - 1 and the four colours as for
+ * mg_fbs_*.  For each colour the corrections c of all its patches solve the
+ * coupled system of Section 5,
+ *     (G + 2 alpha I) c = r,   G_il = <A phi_i, A phi_l>,
+ *     r_i = <b - A u, A phi_i> + 2 alpha d_i,
+ * d_i the tangent-plane estimate of Proposition 1 for patch i (mean of the
+ * signed distances from the patch centre to its 2^(j+2) planes); the system is
+ * solved by cg_iters conjugate-gradient iterations in FP64 from c = 0.
+ * u and b: device arrays of the state dtype, caller-owned, u must not alias b.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t height;       /* H >= 2 */
+    int32_t width;        /* W >= 2 */
+    double alpha;         /* weight of the curvature term, finite and >= 0 */
+    double blur_sigma;    /* width of the Gaussian of A, > 0 */
+    int32_t levels;       /* J in [1, 16] */
+    int32_t state_dtype;  /* mg_dtype of u and b */
+    int32_t cg_iters;     /* CG iterations per colour, [1, 1000] */
+    int32_t reserved;     /* must be 0 */
+} mg_recon_params;
+
+typedef struct mg_recon_ctx mg_recon_ctx;
+
+/* Defaults: alpha 0.01, blur_sigma 1, J = 3, float state, 20 CG iterations. */
+void mg_recon_default_params(mg_recon_params *p, int32_t height, int32_t width);
+
+/* Validate, bind the current device and stream, allocate three H x W FP64
+ * images, one state-dtype image and per-patch CG vectors.  Errors as mg_curv_init. */
+mg_status mg_recon_init(const mg_recon_params *params, void *hip_stream, mg_recon_ctx **out);
+
+/* One colour of one level, in place (enqueued only). */
+mg_status mg_recon_sweep(mg_recon_ctx *ctx, void *u, const void *b, int32_t level, int32_t colour);
+
+/* One V-cycle (levels 1..J, four colours each), replayed from a graph captured
+ * once per (u, b); the energy afterwards into *energy_after if non-null (waits). */
+mg_status mg_recon_vcycle(mg_recon_ctx *ctx, void *u, const void *b, double *energy_after);
+
+/* 1/2 ||A u - b||^2 + alpha sum |H(u)| in FP64. */
+mg_status mg_recon_energy(mg_recon_ctx *ctx, const void *u, const void *b, double *energy);
+
+/* V-cycles until ||u_l - u_{l-1}||_2 < tol ||u_l||_2 (Section 4's relErr(u)) or
+ * max_vcycles; outputs nullable.  MG_OK, MG_NOT_CONVERGED or an error. */
+mg_status mg_recon_solve(mg_recon_ctx *ctx, void *u, const void *b, double tol, int32_t max_vcycles,
+                         int32_t *vcycles_done, double *final_energy);
+
+void mg_recon_destroy(mg_recon_ctx *ctx);
+const char *mg_recon_last_error(const mg_recon_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

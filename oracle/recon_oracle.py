@@ -60,8 +60,10 @@ def apply_At(v: np.ndarray, w: np.ndarray) -> np.ndarray:
 
 
 class ReconOracle:
-    def __init__(self, height: int, width: int, alpha: float, sigma_a: float = 1.0, levels: int = 3):
+    def __init__(self, height: int, width: int, alpha: float, sigma_a: float = 1.0, levels: int = 3,
+                 round_f32: bool = False):
         self.h, self.w, self.alpha, self.levels = height, width, float(alpha), levels
+        self.round_f32 = round_f32   # round the state to float after each update
         self.wts = blur_weights(sigma_a)
         # the tangent-plane estimate and the patch geometry of the paper's local step
         self.fbs = FbsOracle(height, width, 1.0, 0, levels=levels)
@@ -103,6 +105,8 @@ class ReconOracle:
         for (p, q), ci in zip(ps, c):
             r0, r1, c0, c1 = self.fbs.block_bounds(level, p, q)
             u[r0:r1, c0:c1] += ci
+            if self.round_f32:
+                u[r0:r1, c0:c1] = u[r0:r1, c0:c1].astype(np.float32).astype(np.float64)
             cgrid[p, q] = ci
         return cgrid
 

@@ -37,6 +37,11 @@ class MgFbsParams(C.Structure):
 MG_STOP_ENERGY, MG_STOP_RELERR_U = 0, 1
 
 
+class MgReconParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double), ("blur_sigma", C.c_double),
+                ("levels", C.c_int32), ("state_dtype", C.c_int32), ("cg_iters", C.c_int32), ("reserved", C.c_int32)]
+
+
 class MgCurvError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -144,6 +149,23 @@ def _load() -> C.CDLL:
     L.mg_fbs_destroy.argtypes = [vp]
     L.mg_fbs_last_error.restype = C.c_char_p
     L.mg_fbs_last_error.argtypes = [vp]
+    RP = C.POINTER(MgReconParams)
+    L.mg_recon_default_params.restype = None
+    L.mg_recon_default_params.argtypes = [RP, C.c_int32, C.c_int32]
+    L.mg_recon_init.restype = C.c_int
+    L.mg_recon_init.argtypes = [RP, vp, C.POINTER(vp)]
+    L.mg_recon_sweep.restype = C.c_int
+    L.mg_recon_sweep.argtypes = [vp, vp, cvp, C.c_int32, C.c_int32]
+    L.mg_recon_vcycle.restype = C.c_int
+    L.mg_recon_vcycle.argtypes = [vp, vp, cvp, C.POINTER(C.c_double)]
+    L.mg_recon_energy.restype = C.c_int
+    L.mg_recon_energy.argtypes = [vp, cvp, cvp, C.POINTER(C.c_double)]
+    L.mg_recon_solve.restype = C.c_int
+    L.mg_recon_solve.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.mg_recon_destroy.restype = None
+    L.mg_recon_destroy.argtypes = [vp]
+    L.mg_recon_last_error.restype = C.c_char_p
+    L.mg_recon_last_error.argtypes = [vp]
     return L
 
 
@@ -389,6 +411,94 @@ class FbsSolver:
 
     def solve(self, u, f, tol=1e-4, max_vcycles=1000, stop=MG_STOP_RELERR_U, trace=False):
         return mg_fbs_solve(self.ctx, self.params, u, f, tol, max_vcycles, stop, trace)
+
+
+# --- reconstruction b = A u + noise (Section 5) ---------------------------------------
+
+def _rcheck(status: int, ctx=None) -> int:
+    if status < 0:
+        raise MgCurvError(status, lib.mg_recon_last_error(ctx).decode())
+    return status
+
+
+def recon_default_params(height: int, width: int, **kw) -> MgReconParams:
+    p = MgReconParams()
+    lib.mg_recon_default_params(C.byref(p), height, width)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def mg_recon_init(params: MgReconParams, stream=None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    _rcheck(lib.mg_recon_init(C.byref(params), C.c_void_p(_stream_handle(stream)), C.byref(ctx)))
+    return ctx
+
+
+def mg_recon_sweep(ctx, params, u, b, level: int, colour: int) -> None:
+    _rcheck(lib.mg_recon_sweep(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(b, params, "b"), level, colour), ctx)
+
+
+def mg_recon_vcycle(ctx, params, u, b, want_energy: bool = False):
+    e = C.c_double()
+    _rcheck(lib.mg_recon_vcycle(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(b, params, "b"),
+                                C.byref(e) if want_energy else None), ctx)
+    return e.value if want_energy else None
+
+
+def mg_recon_energy(ctx, params, u, b) -> float:
+    e = C.c_double()
+    _rcheck(lib.mg_recon_energy(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(b, params, "b"), C.byref(e)), ctx)
+    return e.value
+
+
+def mg_recon_solve(ctx, params, u, b, tol: float = 1e-4, max_vcycles: int = 200):
+    done = C.c_int32()
+    fin = C.c_double()
+    st = _rcheck(lib.mg_recon_solve(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(b, params, "b"), tol, max_vcycles,
+                                    C.byref(done), C.byref(fin)), ctx)
+    return {"status": st, "vcycles": done.value, "energy": fin.value}
+
+
+def mg_recon_destroy(ctx) -> None:
+    lib.mg_recon_destroy(ctx)
+
+
+class ReconSolver:
+    """Reconstruction from b = A u + noise with a 5 x 5 Gaussian blur as A (one context per size)."""
+
+    def __init__(self, height: int, width: int, alpha: float = 0.01, blur_sigma: float = 1.0, levels: int = 3,
+                 dtype=torch.float32, cg_iters: int = 20, stream=None):
+        self.params = recon_default_params(height, width, alpha=float(alpha), blur_sigma=float(blur_sigma),
+                                           levels=int(levels), state_dtype=MG_F64 if dtype == torch.float64 else MG_F32,
+                                           cg_iters=int(cg_iters))
+        self.dtype = dtype
+        self.ctx = mg_recon_init(self.params, stream)
+
+    def close(self):
+        if self.ctx:
+            mg_recon_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, u, b, level, colour):
+        return mg_recon_sweep(self.ctx, self.params, u, b, level, colour)
+
+    def vcycle(self, u, b, want_energy=False):
+        return mg_recon_vcycle(self.ctx, self.params, u, b, want_energy)
+
+    def energy(self, u, b):
+        return mg_recon_energy(self.ctx, self.params, u, b)
+
+    def solve(self, u, b, tol=1e-4, max_vcycles=200):
+        return mg_recon_solve(self.ctx, self.params, u, b, tol, max_vcycles)
 
 
 # --- batched images ----------------------------------------------------------------

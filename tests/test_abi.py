@@ -202,3 +202,45 @@ def test_fbs_null_arguments_and_no_device(lib):
     lib.mg_fbs_default_params(C.byref(p), 64, 64)
     assert lib.mg_fbs_init(C.byref(p), None, C.byref(ctx)) == -5
     assert b"device" in lib.mg_fbs_last_error(None).lower()
+
+
+class ReconParams(C.Structure):
+    _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double), ("blur_sigma", C.c_double),
+                ("levels", C.c_int32), ("state_dtype", C.c_int32), ("cg_iters", C.c_int32), ("reserved", C.c_int32)]
+
+
+def _recon(lib):
+    lib.mg_recon_init.restype = C.c_int
+    lib.mg_recon_init.argtypes = [C.POINTER(ReconParams), C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.mg_recon_default_params.argtypes = [C.POINTER(ReconParams), C.c_int32, C.c_int32]
+    lib.mg_recon_last_error.restype = C.c_char_p
+    lib.mg_recon_last_error.argtypes = [C.c_void_p]
+    for name in ("mg_recon_vcycle", "mg_recon_energy", "mg_recon_sweep", "mg_recon_solve"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+def test_recon_params_layout_and_validation(lib):
+    import torch
+    _recon(lib)
+    assert C.sizeof(ReconParams) == 40
+    p = ReconParams()
+    lib.mg_recon_default_params(C.byref(p), 32, 24)
+    assert (p.height, p.width, p.alpha, p.blur_sigma, p.levels, p.state_dtype, p.cg_iters, p.reserved) == \
+        (32, 24, 0.01, 1.0, 3, 0, 20, 0)
+    for field, value, status in [("height", 1, -2), ("alpha", -1.0, -1), ("blur_sigma", 0.0, -1),
+                                 ("state_dtype", 3, -3), ("levels", 0, -1), ("cg_iters", 0, -1), ("reserved", 2, -1)]:
+        q = ReconParams()
+        lib.mg_recon_default_params(C.byref(q), 32, 24)
+        setattr(q, field, value)
+        ctx = C.c_void_p(99)
+        assert lib.mg_recon_init(C.byref(q), None, C.byref(ctx)) == status, field
+        assert not ctx.value
+    ctx = C.c_void_p()
+    assert lib.mg_recon_init(None, None, C.byref(ctx)) == -1
+    assert lib.mg_recon_vcycle(None, None, None, None) == -1
+    assert lib.mg_recon_energy(None, None, None, None) == -1
+    assert lib.mg_recon_sweep(None, None, None, 1, 0) == -1
+    lib.mg_recon_destroy(None)
+    if not torch.cuda.is_available():
+        assert lib.mg_recon_init(C.byref(p), None, C.byref(ctx)) == -5
