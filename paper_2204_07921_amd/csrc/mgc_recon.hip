@@ -34,6 +34,7 @@ constexpr int NW = (2 * RB + 1) * (2 * RB + 1);
 
 struct Blur {
     double w[NW];   // w[(dy + 2) * 5 + dx + 2]: (A u)(p) = sum w[o] u(p + o)
+    double g[5];    // 1-D factor: the normalised Gaussian is g[dy + 2] g[dx + 2]
 };
 
 // Patches of colour k of a level with side b: index g -> patch (p, q).
@@ -82,14 +83,19 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return block_total<NT>(x, lds);
 }
 
+// Pixel kernels run on a 2-D grid: x over columns, y over rows (row-strided), so
+// no pixel index is ever divided.
+#define REC_PIXELS                                                          \
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;                     \
+    if (j >= W) return;                                                      \
+    for (int i = blockIdx.y; i < H; i += gridDim.y)
+
 // t = b - A u
 template <typename T>
 __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ u, const T* __restrict__ b, int H, int W,
                                                        Blur bl, double* __restrict__ t)
 {
-    const size_t n = (size_t)H * W;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / W), j = (int)(k - (size_t)i * W);
+    REC_PIXELS {
         double acc = 0.0;
 #pragma unroll
         for (int dy = -RB; dy <= RB; ++dy) {
@@ -102,43 +108,55 @@ __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ u, 
                 acc += bl.w[(dy + RB) * 5 + dx + RB] * (double)u[(size_t)ii * W + jj];
             }
         }
+        const size_t k = (size_t)i * W + j;
         t[k] = (double)b[k] - acc;
     }
 }
 
-// w = A v for an FP64 image v
-__global__ __launch_bounds__(256) void blur_kernel(const double* __restrict__ v, int H, int W, Blur bl,
-                                                   double* __restrict__ w)
+// w = A v with v = sum over colour-k patches of pv_i phi_i (zero elsewhere and outside)
+__global__ __launch_bounds__(256) void blur_expand_kernel(const double* __restrict__ pv, int H, int W, ColourGrid cg,
+                                                          Blur bl, double* __restrict__ w)
 {
-    const size_t n = (size_t)H * W;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / W), j = (int)(k - (size_t)i * W);
+    REC_PIXELS {
+        // patch row / column of the five rows and columns around (i, j), and whether they have colour k
+        int prow[5], pcol[5];
+        bool rok[5], cok[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            const int ii = i + d - RB, jj = j + d - RB;
+            rok[d] = ii >= 0 && ii < H;
+            cok[d] = jj >= 0 && jj < W;
+            prow[d] = rok[d] ? ii / cg.b : 0;
+            pcol[d] = cok[d] ? jj / cg.b : 0;
+            rok[d] = rok[d] && (prow[d] & 1) == cg.pr;
+            cok[d] = cok[d] && (pcol[d] & 1) == cg.pc;
+        }
         double acc = 0.0;
 #pragma unroll
-        for (int dy = -RB; dy <= RB; ++dy) {
-            const int ii = i + dy;
-            if (ii < 0 || ii >= H) continue;
+        for (int dy = 0; dy < 5; ++dy) {
+            if (!rok[dy]) continue;
+            const double* row = pv + (size_t)prow[dy] * cg.nj;
 #pragma unroll
-            for (int dx = -RB; dx <= RB; ++dx) {
-                const int jj = j + dx;
-                if (jj < 0 || jj >= W) continue;
-                acc += bl.w[(dy + RB) * 5 + dx + RB] * v[(size_t)ii * W + jj];
-            }
+            for (int dx = 0; dx < 5; ++dx)
+                if (cok[dx]) acc += bl.w[dy * 5 + dx] * row[pcol[dx]];
         }
-        w[k] = acc;
+        w[(size_t)i * W + j] = acc;
     }
 }
 
-// v = sum over colour-k patches of pv_i phi_i (zero on other pixels)
-__global__ __launch_bounds__(256) void expand_kernel(const double* __restrict__ pv, int H, int W, ColourGrid cg,
-                                                     double* __restrict__ v)
+// Squared norm of the blurred indicator of rows [a, e) of an image of n rows,
+// one factor of <A phi, A phi> (the Gaussian is separable).
+__device__ __forceinline__ double blur_factor(const Blur& bl, int a, int e, int n)
 {
-    const size_t n = (size_t)H * W;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / W), j = (int)(k - (size_t)i * W);
-        const int p = i / cg.b, q = j / cg.b;
-        v[k] = ((p & 1) == cg.pr && (q & 1) == cg.pc) ? pv[(size_t)p * cg.nj + q] : 0.0;
+    double s = 0.0;
+    for (int i = max(0, a - RB); i < min(n, e + RB); ++i) {
+        double r = 0.0;
+#pragma unroll
+        for (int d = -RB; d <= RB; ++d)
+            if (i + d >= a && i + d < e) r += bl.g[d + RB];
+        s += r * r;
     }
+    return s;
 }
 
 // Patch (p, q) of a colour-grid index.
@@ -178,11 +196,15 @@ __device__ __forceinline__ double patch_adjoint_sum(const double* __restrict__ i
 
 // d_i (Proposition 1 on the patch's rings), r_i = sum_patch A^T t + 2 alpha d_i,
 // x_i = 0, p_i = r_i, and per-workgroup partials of r . r.
+// With `diagonal` (patch side >= 5: the blurred indicators of two patches of one
+// colour, each reaching 2 pixels beyond its patch, are separated by a gap of b >= 5
+// pixels and never overlap, so G is diagonal) the kernel solves directly:
+// x_i = r_i / (<A phi_i, A phi_i> + 2 alpha).
 template <typename T, int G>
 __global__ __launch_bounds__(256) void rhs_kernel(const T* __restrict__ u, const double* __restrict__ t, int H, int W,
-                                                  Blur bl, ColourGrid cg, double alpha, double* __restrict__ x,
-                                                  double* __restrict__ r, double* __restrict__ pv,
-                                                  double* __restrict__ part_rr)
+                                                  Blur bl, ColourGrid cg, double alpha, int diagonal,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ pv, double* __restrict__ part_rr)
 {
     __shared__ double lds[4];
     const int gid = (int)((blockIdx.x * blockDim.x + threadIdx.x) / G), lane = threadIdx.x % G;
@@ -212,10 +234,15 @@ __global__ __launch_bounds__(256) void rhs_kernel(const T* __restrict__ u, const
         const double ri = patch_adjoint_sum<G>(t, H, W, bl, r0, r1, c0, c1, lane) + 2.0 * alpha * d;
         const size_t id = (size_t)p * cg.nj + q;
         if (lane == 0) {
-            x[id] = 0.0;
-            r[id] = ri;
-            pv[id] = ri;
-            rr = ri * ri;
+            if (diagonal) {
+                const double gii = blur_factor(bl, r0, r1, H) * blur_factor(bl, c0, c1, W);
+                x[id] = ri / (gii + 2.0 * alpha);
+            } else {
+                x[id] = 0.0;
+                r[id] = ri;
+                pv[id] = ri;
+                rr = ri * ri;
+            }
         }
     } else {
         // keep the group's shuffles complete for lanes of a dead group
@@ -312,47 +339,48 @@ template <typename T>
 __global__ __launch_bounds__(256) void apply_kernel(T* __restrict__ u, int H, int W, ColourGrid cg,
                                                     const double* __restrict__ x)
 {
-    const size_t n = (size_t)H * W;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / W), j = (int)(k - (size_t)i * W);
+    REC_PIXELS {
         const int p = i / cg.b, q = j / cg.b;
         if ((p & 1) == cg.pr && (q & 1) == cg.pc) {
             const double c = x[(size_t)p * cg.nj + q];
+            const size_t k = (size_t)i * W + j;
             if (c != 0.0) u[k] = (T)((double)u[k] + c);
         }
     }
 }
 
-// Energy partials: 1/2 (A u - b)^2 + alpha |kappa_MC(u)|
+// Energy partials: 1/2 (A u - b)^2 + alpha |kappa_MC(u)|, one partial per workgroup
 template <typename T>
 __global__ __launch_bounds__(256) void energy_kernel(const T* __restrict__ u, const T* __restrict__ b, int H, int W,
                                                      Blur bl, double alpha, double* __restrict__ part)
 {
     __shared__ double lds[4];
-    const size_t n = (size_t)H * W;
     double acc = 0.0;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(k / W), j = (int)(k - (size_t)i * W);
-        double a = 0.0;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < W; j += gridDim.x * blockDim.x) {
+        for (int i = blockIdx.y; i < H; i += gridDim.y) {
+            double a = 0.0;
 #pragma unroll
-        for (int dy = -RB; dy <= RB; ++dy) {
-            const int ii = i + dy;
-            if (ii < 0 || ii >= H) continue;
+            for (int dy = -RB; dy <= RB; ++dy) {
+                const int ii = i + dy;
+                if (ii < 0 || ii >= H) continue;
 #pragma unroll
-            for (int dx = -RB; dx <= RB; ++dx) {
-                const int jj = j + dx;
-                if (jj < 0 || jj >= W) continue;
-                a += bl.w[(dy + RB) * 5 + dx + RB] * (double)u[(size_t)ii * W + jj];
+                for (int dx = -RB; dx <= RB; ++dx) {
+                    const int jj = j + dx;
+                    if (jj < 0 || jj >= W) continue;
+                    a += bl.w[(dy + RB) * 5 + dx + RB] * (double)u[(size_t)ii * W + jj];
+                }
             }
+            const double res = a - (double)b[(size_t)i * W + j];
+            acc += 0.5 * res * res + alpha * mgc::abs_kappa_at<0>(u, H, W, i, j);
         }
-        const double res = a - (double)b[k];
-        acc += 0.5 * res * res + alpha * mgc::abs_kappa_at<0>(u, H, W, i, j);
     }
     const double tot = block_total<256>(acc, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
-constexpr int GRID_PIX = 2048;   // workgroups of the pixel-wise kernels (grid-stride)
+constexpr int GRID_PIX = 2048;   // partial sums of the energy and of the norms
+
+inline dim3 pixel_grid(int H, int W) { return dim3((W + 255) / 256, H < 1024 ? H : 1024); }
 
 }  // namespace rec
 
@@ -366,7 +394,6 @@ struct mg_recon_ctx {
     hipStream_t gstream;     // own stream, only for capturing graphs (default priority)
     rec::Blur blur;
     double* t;               // H x W FP64: b - A u
-    double* v;               // H x W FP64: expanded search direction
     double* w;               // H x W FP64: A v
     double* x;               // patch arrays (largest level grid)
     double* r;
@@ -435,7 +462,8 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     const int G = lanes_for(bs);
     const int ng = groups_grid(n, G);        // workgroups of the patch-wise kernels
     const int nv = (n + 255) / 256;          // workgroups of the vector kernels
-    const dim3 blk(256), gp(rec::GRID_PIX);
+    const dim3 blk(256), gp = rec::pixel_grid(H, W);
+    const int diagonal = bs >= 5;
     hipLaunchKernelGGL(rec::residual_kernel<T>, gp, blk, 0, st, (const T*)u, (const T*)b, H, W, c->blur, c->t);
 #define REC_G(KERNEL, ...)                                                                        \
     switch (G) {                                                                                  \
@@ -445,16 +473,15 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     default: hipLaunchKernelGGL((KERNEL<256>), dim3(ng), blk, 0, st, __VA_ARGS__); break;        \
     }
     switch (G) {
-    case 1: hipLaunchKernelGGL((rec::rhs_kernel<T, 1>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, c->x, c->r, c->pv, c->part_b); break;
-    case 8: hipLaunchKernelGGL((rec::rhs_kernel<T, 8>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, c->x, c->r, c->pv, c->part_b); break;
-    case 64: hipLaunchKernelGGL((rec::rhs_kernel<T, 64>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, c->x, c->r, c->pv, c->part_b); break;
-    default: hipLaunchKernelGGL((rec::rhs_kernel<T, 256>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, c->x, c->r, c->pv, c->part_b); break;
+    case 1: hipLaunchKernelGGL((rec::rhs_kernel<T, 1>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
+    case 8: hipLaunchKernelGGL((rec::rhs_kernel<T, 8>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
+    case 64: hipLaunchKernelGGL((rec::rhs_kernel<T, 64>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
+    default: hipLaunchKernelGGL((rec::rhs_kernel<T, 256>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
     }
-    hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), blk, 0, st, (const double*)c->part_b, ng, c->scal, 0);
-    for (int it = 0; it < c->P.cg_iters; ++it) {
+    if (!diagonal) hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), blk, 0, st, (const double*)c->part_b, ng, c->scal, 0);
+    for (int it = 0; it < (diagonal ? 0 : c->P.cg_iters); ++it) {
         const int k_old = it & 1, k_new = k_old ^ 1;
-        hipLaunchKernelGGL(rec::expand_kernel, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->v);
-        hipLaunchKernelGGL(rec::blur_kernel, gp, blk, 0, st, (const double*)c->v, H, W, c->blur, c->w);
+        hipLaunchKernelGGL(rec::blur_expand_kernel, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
         REC_G(rec::gram_kernel, (const double*)c->w, H, W, c->blur, cg, c->P.alpha, (const double*)c->pv, c->qv, c->part_a);
         hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, ng,
                            (const double*)c->scal, k_old, c->x, c->r, (const double*)c->pv, (const double*)c->qv, c->part_b);
@@ -486,9 +513,13 @@ mg_status vcycle_enqueue(mg_recon_ctx* c, hipStream_t st, void* u, const void* b
 template <typename T>
 mg_status energy_enqueue_t(mg_recon_ctx* c, hipStream_t st, const void* u, const void* b)
 {
-    hipLaunchKernelGGL(rec::energy_kernel<T>, dim3(rec::GRID_PIX), dim3(256), 0, st, (const T*)u, (const T*)b,
+    // at most 256 x 8 = GRID_PIX workgroups, hence partials
+    const int ex = (c->P.width + 255) / 256;
+    const dim3 eg(ex < 256 ? ex : 256, c->P.height < 8 ? c->P.height : 8);
+    hipLaunchKernelGGL(rec::energy_kernel<T>, eg, dim3(256), 0, st, (const T*)u, (const T*)b,
                        c->P.height, c->P.width, c->blur, c->P.alpha, c->part_a);
-    hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), dim3(256), 0, st, (const double*)c->part_a, rec::GRID_PIX, c->scal, 2);
+    hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), dim3(256), 0, st, (const double*)c->part_a, (int)(eg.x * eg.y),
+                       c->scal, 2);
     hipError_t e = hipMemcpyAsync(c->host1, c->scal + 2, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? MG_OK : rhip(c, e, "energy launch");
@@ -598,7 +629,7 @@ mg_status mg_recon_init(const mg_recon_params* params, void* hip_stream, mg_reco
     c->P = p;
     c->stream = (hipStream_t)hip_stream;
     c->gstream = nullptr;
-    c->t = c->v = c->w = c->x = c->r = c->pv = c->qv = c->part_a = c->part_b = c->scal = c->host1 = nullptr;
+    c->t = c->w = c->x = c->r = c->pv = c->qv = c->part_a = c->part_b = c->scal = c->host1 = nullptr;
     c->norms_part = nullptr;
     c->prev = nullptr;
     c->graph = nullptr;
@@ -614,6 +645,10 @@ mg_status mg_recon_init(const mg_recon_params* params, void* hip_stream, mg_reco
             tot += v;
         }
     for (int k = 0; k < rec::NW; ++k) c->blur.w[k] /= tot;
+    double g1 = 0.0;
+    for (int d = -rec::RB; d <= rec::RB; ++d) g1 += std::exp(-(d * d) / (2.0 * p.blur_sigma * p.blur_sigma));
+    for (int d = -rec::RB; d <= rec::RB; ++d)
+        c->blur.g[d + rec::RB] = std::exp(-(d * d) / (2.0 * p.blur_sigma * p.blur_sigma)) / g1;
     size_t npatch = 1;
     int maxgroups = 1;
     for (int level = 1; level <= p.levels; ++level) {
@@ -628,7 +663,7 @@ mg_status mg_recon_init(const mg_recon_params* params, void* hip_stream, mg_reco
     }
     const size_t img = (size_t)p.height * p.width;
     const size_t npart = (size_t)(maxgroups > rec::GRID_PIX ? maxgroups : rec::GRID_PIX);
-    if (hipMalloc((void**)&c->t, img * 8) != hipSuccess || hipMalloc((void**)&c->v, img * 8) != hipSuccess ||
+    if (hipMalloc((void**)&c->t, img * 8) != hipSuccess ||
         hipMalloc((void**)&c->w, img * 8) != hipSuccess || hipMalloc((void**)&c->x, npatch * 8) != hipSuccess ||
         hipMalloc((void**)&c->r, npatch * 8) != hipSuccess || hipMalloc((void**)&c->pv, npatch * 8) != hipSuccess ||
         hipMalloc((void**)&c->qv, npatch * 8) != hipSuccess || hipMalloc((void**)&c->part_a, npart * 8) != hipSuccess ||
@@ -720,7 +755,7 @@ void mg_recon_destroy(mg_recon_ctx* ctx)
     if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
     drop_graph(ctx);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
-    for (double* q : {ctx->t, ctx->v, ctx->w, ctx->x, ctx->r, ctx->pv, ctx->qv, ctx->part_a, ctx->part_b, ctx->scal,
+    for (double* q : {ctx->t, ctx->w, ctx->x, ctx->r, ctx->pv, ctx->qv, ctx->part_a, ctx->part_b, ctx->scal,
                       ctx->norms_part})
         if (q) (void)hipFree(q);
     if (ctx->prev) (void)hipFree(ctx->prev);
