@@ -513,9 +513,12 @@ mg_status vcycle_enqueue(mg_recon_ctx* c, hipStream_t st, void* u, const void* b
 template <typename T>
 mg_status energy_enqueue_t(mg_recon_ctx* c, hipStream_t st, const void* u, const void* b)
 {
-    // at most 256 x 8 = GRID_PIX workgroups, hence partials
-    const int ex = (c->P.width + 255) / 256;
-    const dim3 eg(ex < 256 ? ex : 256, c->P.height < 8 ? c->P.height : 8);
+    // at most GRID_PIX workgroups (hence partials): columns first, the rest over rows
+    int ex = (c->P.width + 255) / 256;
+    if (ex > rec::GRID_PIX) ex = rec::GRID_PIX;
+    int ey = rec::GRID_PIX / ex;
+    if (ey > c->P.height) ey = c->P.height;
+    const dim3 eg(ex, ey);
     hipLaunchKernelGGL(rec::energy_kernel<T>, eg, dim3(256), 0, st, (const T*)u, (const T*)b,
                        c->P.height, c->P.width, c->blur, c->P.alpha, c->part_a);
     hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), dim3(256), 0, st, (const double*)c->part_a, (int)(eg.x * eg.y),
