@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mgc {
 
 enum { KIND_MEAN = 0, KIND_GAUSS = 1 };
@@ -107,36 +109,95 @@ __device__ __forceinline__ double abs_kappa(const Ring& r, double c)
     }
 }
 
-// d|kappa|/dc = sign(kappa) dkappa/dc at shift c (sign(0) = 0).
-template <int KIND>
-__device__ __forceinline__ double dabs_kappa(const Ring& r, double c)
+// 1/sqrt(q) for finite q > 0: the hardware estimate, then one step of the
+// series 1/sqrt(q) = y (1 - e)^{-1/2} = y (1 + e/2 + 3e^2/8 + ...), e = 1 - q y^2,
+// which takes the estimate to full double precision.
+__device__ __forceinline__ double rsqrt_pos(double q)
 {
-    const double bx = r.b[0], by = r.b[1], bxx = r.b[2], byy = r.b[3], bxy = r.b[4];
-    const double ux = fma(bx, c, r.a[0]);
-    const double uy = fma(by, c, r.a[1]);
-    const double uxx = fma(bxx, c, r.a[2]);
-    const double uyy = fma(byy, c, r.a[3]);
-    const double uxy = fma(bxy, c, r.a[4]);
-    const double q = fma(ux, ux, fma(uy, uy, 1.0));
-    const double dq = 2.0 * fma(ux, bx, uy * by);
-    if (KIND == KIND_MEAN) {
-        const double px = fma(ux, ux, 1.0), py = fma(uy, uy, 1.0);
-        const double num = fma(py, uxx, fma(px, uyy, -2.0 * ux * uy * uxy));
-        const double dnum = 2.0 * uy * by * uxx + py * bxx
-                          - 2.0 * (bx * uy * uxy + ux * by * uxy + ux * uy * bxy)
-                          + 2.0 * ux * bx * uyy + px * byy;
-        const double rq = rsqrt(q);
-        const double r2 = rq * rq;
-        const double dk = fma(-1.5 * num * dq, r2, dnum) * (r2 * rq);
-        const double s = (num > 0.0) ? 1.0 : ((num < 0.0) ? -1.0 : 0.0);
-        return s * dk;
+    const double y = __builtin_amdgcn_rsq(q);
+    const double e = fma(-q * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// sign(n) * v with sign(0) = 0 (the one-sided derivative convention of |kappa|).
+__device__ __forceinline__ double signed_by(double n, double v)
+{
+    const double sg = n > 0.0 ? 1.0 : (n < 0.0 ? -1.0 : 0.0);
+    return sg * v;
+}
+
+// A ring record expanded in powers of c.  With every derivative affine in c,
+//   q(c) = 1 + u_x^2 + u_y^2                                   quadratic,
+//   mean:     N(c) = (1 + u_y^2) u_xx + (1 + u_x^2) u_yy - 2 u_x u_y u_xy   cubic,   kappa = N q^{-3/2},
+//   Gaussian: D(c) = u_xx u_yy - u_xy^2                        quadratic, kappa = D q^{-2}.
+// The expansion is done once per record; an evaluation is then a few Horner
+// steps, and the record holds 7 (mean) or 6 (Gaussian) doubles instead of 10.
+template <int KIND>
+struct PolyRing {
+    double q0, q1, q2;
+    double n[KIND == KIND_MEAN ? 4 : 3];
+};
+
+template <int KIND>
+__device__ __forceinline__ void make_poly(const Ring& r, PolyRing<KIND>& p)
+{
+    const double a0 = r.a[0], a1 = r.a[1], a2 = r.a[2], a3 = r.a[3], a4 = r.a[4];
+    const double b0 = r.b[0], b1 = r.b[1], b2 = r.b[2], b3 = r.b[3], b4 = r.b[4];
+    p.q0 = fma(a0, a0, fma(a1, a1, 1.0));
+    p.q1 = 2.0 * fma(a0, b0, a1 * b1);
+    p.q2 = fma(b0, b0, b1 * b1);
+    if constexpr (KIND == KIND_MEAN) {
+        // 1 + u_y^2, 1 + u_x^2 and u_x u_y as quadratics in c
+        const double py0 = fma(a1, a1, 1.0), py1 = 2.0 * a1 * b1, py2 = b1 * b1;
+        const double px0 = fma(a0, a0, 1.0), px1 = 2.0 * a0 * b0, px2 = b0 * b0;
+        const double m0 = a0 * a1, m1 = fma(a0, b1, b0 * a1), m2 = b0 * b1;
+        p.n[0] = fma(py0, a2, px0 * a3) - 2.0 * (m0 * a4);
+        p.n[1] = (fma(py0, b2, py1 * a2) + fma(px0, b3, px1 * a3)) - 2.0 * fma(m0, b4, m1 * a4);
+        p.n[2] = (fma(py1, b2, py2 * a2) + fma(px1, b3, px2 * a3)) - 2.0 * fma(m1, b4, m2 * a4);
+        p.n[3] = fma(py2, b2, px2 * b3) - 2.0 * (m2 * b4);
     } else {
-        const double det = fma(uxx, uyy, -uxy * uxy);
-        const double ddet = bxx * uyy + uxx * byy - 2.0 * uxy * bxy;
-        const double iq = 1.0 / q;
-        const double dk = fma(-2.0 * det * dq, iq, ddet) * (iq * iq);
-        const double s = (det > 0.0) ? 1.0 : ((det < 0.0) ? -1.0 : 0.0);
-        return s * dk;
+        p.n[0] = fma(a2, a3, -a4 * a4);
+        p.n[1] = fma(a2, b3, b2 * a3) - 2.0 * (a4 * b4);
+        p.n[2] = fma(b2, b3, -b4 * b4);
+    }
+}
+
+// |kappa| of an expanded record at shift c.
+template <int KIND>
+__device__ __forceinline__ double abs_poly(const PolyRing<KIND>& p, double c)
+{
+    const double q = fma(fma(p.q2, c, p.q1), c, p.q0);
+    const double rq = rsqrt_pos(q);
+    if constexpr (KIND == KIND_MEAN) {
+        const double num = fma(fma(fma(p.n[3], c, p.n[2]), c, p.n[1]), c, p.n[0]);
+        return fabs(num) * (rq * rq * rq);
+    } else {
+        const double det = fma(fma(p.n[2], c, p.n[1]), c, p.n[0]);
+        const double r2 = rq * rq;
+        return fabs(det) * (r2 * r2);
+    }
+}
+
+// d|kappa|/dc = sign(kappa) dkappa/dc at shift c (sign(0) = 0):
+//   mean:     (N' q - 3/2 N q') q^{-5/2},   Gaussian: (D' q - 2 D q') q^{-3}.
+template <int KIND>
+__device__ __forceinline__ double dabs_poly(const PolyRing<KIND>& p, double c)
+{
+    const double c2 = c + c;
+    const double q = fma(fma(p.q2, c, p.q1), c, p.q0);
+    const double dq = fma(p.q2, c2, p.q1);
+    const double rq = rsqrt_pos(q);
+    const double r2 = rq * rq;
+    if constexpr (KIND == KIND_MEAN) {
+        const double num = fma(fma(fma(p.n[3], c, p.n[2]), c, p.n[1]), c, p.n[0]);
+        const double dnum = fma(p.n[2], c2, fma(p.n[3], 3.0 * (c * c), p.n[1]));
+        const double t = fma(-1.5 * num, dq, dnum * q);
+        return signed_by(num, t * (r2 * r2 * rq));
+    } else {
+        const double det = fma(fma(p.n[2], c, p.n[1]), c, p.n[0]);
+        const double ddet = fma(p.n[2], c2, p.n[1]);
+        const double t = fma(-2.0 * det, dq, ddet * q);
+        return signed_by(det, t * (r2 * r2 * r2));
     }
 }
 
@@ -165,8 +226,9 @@ __device__ __forceinline__ double abs_kappa_at(const T* __restrict__ u, int H, i
 // identical branches in the local solver.  sum(x) reduces one value,
 // sum_n<N>(x) reduces N values with one synchronisation.
 // ---------------------------------------------------------------------------
-template <int GROUP>
+template <int GROUP, int CHUNK_ = 8>
 struct WaveSum {
+    static constexpr int CHUNK = CHUNK_;   // samples per fused reduction in local_solve
     __device__ __forceinline__ double operator()(double x) const
     {
 #pragma unroll
@@ -188,6 +250,7 @@ template <int GROUP>
 struct BlockSum {
     static constexpr int NW = GROUP / 64;
     static constexpr int NMAX = 8;   // values per sum_n
+    static constexpr int CHUNK = 8;
     double* lds;   // 2 * NW * NMAX doubles
     mutable int parity;
     __device__ __forceinline__ double operator()(double x) const
@@ -225,6 +288,7 @@ struct BlockSum {
 
 // Single lane (pixel level): nothing to reduce.
 struct NoSum {
+    static constexpr int CHUNK = 1;   // nothing to fuse; fewer live registers
     __device__ __forceinline__ double operator()(double x) const { return x; }
     template <int N>
     __device__ __forceinline__ void sum_n(double (&)[N]) const {}
@@ -248,7 +312,7 @@ struct NoSum {
 template <class KP, class DP, class GS>
 __device__ __forceinline__ double local_solve(KP&& Kpart, DP&& Dpart, const GS& gs, double fs, double as, int M, int G)
 {
-    constexpr int CH = 8;  // samples per fused reduction
+    constexpr int CH = GS::CHUNK;  // samples per fused reduction
     double k2[2];
     {
         const double c2[2] = {0.0, fs};
@@ -266,52 +330,65 @@ __device__ __forceinline__ double local_solve(KP&& Kpart, DP&& Dpart, const GS& 
         Kt = Kf;
     } else {
         // samples i = 0..M except M/2 (= f*, already known), CH per fused reduction,
-        // scanned in increasing i so that ties keep the first index
-        double vbest = 0.0, kbest = 0.0;
-        int istar = -1;
-        auto consider = [&](int i, double ci, double ki) {
-            const double vi = ki + 0.5 * as * (ci - fs) * (ci - fs);
-            if (istar < 0 || vi < vbest) { vbest = vi; kbest = ki; istar = i; }
+        // scanned in increasing i so that ties keep the first index.  The sample
+        // offsets (2i - M) / M are the rounded quotients; for M a power of two the
+        // product with the exact 1/M is the same number, so that case (the usual
+        // one) gets its own copy of the loops without the division.
+        auto scan = [&](auto pow2) {
+            constexpr bool P2 = decltype(pow2)::value;
+            const double invm = 1.0 / (double)M;
+            auto frac = [&](int i) {
+                const double n = (double)(2 * i - M);
+                return P2 ? n * invm : n / (double)M;
+            };
+            double vbest = 0.0, kbest = 0.0;
+            int istar = -1;
+            auto consider = [&](int i, double ci, double ki) {
+                const double vi = ki + 0.5 * as * (ci - fs) * (ci - fs);
+                if (istar < 0 || vi < vbest) { vbest = vi; kbest = ki; istar = i; }
+            };
+            for (int t0 = 0; t0 < M; t0 += CH) {
+                double cs[CH], ks[CH];
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
+                    const int tt = t0 + t < M ? t0 + t : M - 1;
+                    const int i = tt < M / 2 ? tt : tt + 1;
+                    cs[t] = fs + rho * frac(i);
+                }
+                Kpart(cs, ks);
+                gs.template sum_n<CH>(ks);
+#pragma unroll
+                for (int t = 0; t < CH; ++t) {
+                    const int tt = t0 + t;
+                    if (tt >= M) break;
+                    const int i = tt < M / 2 ? tt : tt + 1;
+                    if (i == M / 2 + 1) consider(M / 2, fs, Kf);
+                    consider(i, cs[t], ks[t]);
+                }
+            }
+            const double cbest = fs + rho * frac(istar);
+            const int ilo = istar > 0 ? istar - 1 : 0;
+            const int ihi = istar < M ? istar + 1 : M;
+            double lo = fs + rho * frac(ilo);
+            double hi = fs + rho * frac(ihi);
+            for (int g = 0; g < G; ++g) {
+                const double mid = 0.5 * (lo + hi);
+                const double d = gs(Dpart(mid)) + as * (mid - fs);
+                if (d > 0.0) hi = mid; else lo = mid;
+            }
+            const double cbis = 0.5 * (lo + hi);
+            double kb[1];
+            {
+                const double cb[1] = {cbis};
+                Kpart(cb, kb);
+                gs.template sum_n<1>(kb);
+            }
+            const double vbis = kb[0] + 0.5 * as * (cbis - fs) * (cbis - fs);
+            if (vbest < vbis - eta) { ct = cbest; Kt = kbest; }
+            else { ct = cbis; Kt = kb[0]; }
         };
-        for (int t0 = 0; t0 < M; t0 += CH) {
-            double cs[CH], ks[CH];
-#pragma unroll
-            for (int t = 0; t < CH; ++t) {
-                const int tt = t0 + t < M ? t0 + t : M - 1;
-                const int i = tt < M / 2 ? tt : tt + 1;
-                cs[t] = fs + rho * ((double)(2 * i - M) / (double)M);
-            }
-            Kpart(cs, ks);
-            gs.template sum_n<CH>(ks);
-#pragma unroll
-            for (int t = 0; t < CH; ++t) {
-                const int tt = t0 + t;
-                if (tt >= M) break;
-                const int i = tt < M / 2 ? tt : tt + 1;
-                if (i == M / 2 + 1) consider(M / 2, fs, Kf);
-                consider(i, cs[t], ks[t]);
-            }
-        }
-        const double cbest = fs + rho * ((double)(2 * istar - M) / (double)M);
-        const int ilo = istar > 0 ? istar - 1 : 0;
-        const int ihi = istar < M ? istar + 1 : M;
-        double lo = fs + rho * ((double)(2 * ilo - M) / (double)M);
-        double hi = fs + rho * ((double)(2 * ihi - M) / (double)M);
-        for (int g = 0; g < G; ++g) {
-            const double mid = 0.5 * (lo + hi);
-            const double d = gs(Dpart(mid)) + as * (mid - fs);
-            if (d > 0.0) hi = mid; else lo = mid;
-        }
-        const double cbis = 0.5 * (lo + hi);
-        double kb[1];
-        {
-            const double cb[1] = {cbis};
-            Kpart(cb, kb);
-            gs.template sum_n<1>(kb);
-        }
-        const double vbis = kb[0] + 0.5 * as * (cbis - fs) * (cbis - fs);
-        if (vbest < vbis - eta) { ct = cbest; Kt = kbest; }
-        else { ct = cbis; Kt = kb[0]; }
+        if ((M & (M - 1)) == 0) scan(std::true_type());
+        else scan(std::false_type());
     }
     const double delta = (Kt - K0) + 0.5 * as * ct * (ct - 2.0 * fs);
     return delta < eta ? ct : 0.0;

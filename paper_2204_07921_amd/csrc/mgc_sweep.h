@@ -10,18 +10,20 @@ namespace mgc {
 // Pixel level, pixel (i, j) not on the image border.  Exactly one tap of each
 // ring pixel's stencil is (i, j) itself, so the slopes beta are constants of
 // the ring position:  centre: u_xx, u_yy slope -2;  east/west neighbour: u_x
-// slope -dx/2, u_xx slope 1;  north/south: u_y slope -dy/2, u_yy slope 1;
+// slope -+1/2, u_xx slope 1;  south/north: u_y slope -+1/2, u_yy slope 1;
 // diagonal (dy, dx): u_xy slope dy dx / 4.  For the centre and the diagonals
-// q = 1 + |grad u|^2 does not move with c, so their curvature is
-//   mean:      kappa(c) = (N0 + Nc c) q^{-3/2}            (linear in c)
-//   Gaussian:  kappa(c) = det(c) / q^2, det quadratic in c.
-// Only the four edge neighbours need the full rational evaluation.
+// q = 1 + |grad u|^2 does not move with c, so their curvature is a polynomial
+// in c (mean: linear, Gaussian: quadratic) whose coefficients already carry the
+// constant factor q^{-3/2} or q^{-2}.  For an edge neighbour let w be its
+// moving first derivative (u_x for E/W, u_y for S/N), w = w0 + s c with
+// s = -+1/2, and p = 1 + (the other first derivative)^2.  Then q = p + w^2 and
+//   mean:     N = p c + P0 + w (A w + k),  A = the fixed second derivative
+//             along w's axis' complement, k = -2 (other first derivative) u_xy;
+//   Gaussian: D = D1 c + D0 (linear).
 template <int KIND>
 struct PixelRing {
-    double n0[5], nc[5], r[5];   // centre (0) and diagonals (1..4): mean N0, Nc, q^{-3/2};
-                                 // Gaussian: centre n0 = u_xx, nc = u_yy, corners n0 = u_xx u_yy, nc = u_xy
-    double m[5];                 // Gaussian: centre -u_xy^2; corners dy*dx
-    double e[4][5];              // edge neighbours E, W, S, N: derivatives at c = 0
+    double g[5][KIND == KIND_MEAN ? 2 : 3];   // centre (0), diagonals (1..4): kappa = sum_m g[m] c^m
+    double e[4][KIND == KIND_MEAN ? 5 : 4];   // E, W, S, N: mean {w0, p, P0, A, k}, Gaussian {w0, p, D0, D1}
 };
 
 __device__ __forceinline__ void stencil_at(const double w[5][5], int r, int c, double d[5])
@@ -33,42 +35,70 @@ __device__ __forceinline__ void stencil_at(const double w[5][5], int r, int c, d
     d[4] = 0.25 * ((w[r + 1][c + 1] - w[r - 1][c + 1]) - (w[r + 1][c - 1] - w[r - 1][c - 1]));
 }
 
-// edge neighbour k (0 E, 1 W, 2 S, 3 N): derivatives moved by c with constant slopes
+// edge neighbour K (0 E, 1 W, 2 S, 3 N): slope of its moving first derivative
 template <int K>
-__device__ __forceinline__ void edge_derivs(const double a[5], double c, double d[5], double bd[5])
+struct EdgeSlope {
+    static constexpr double s = (K == 0 || K == 2) ? -0.5 : 0.5;
+};
+
+template <int KIND, int K>
+__device__ __forceinline__ void make_edge(const double d[5], double e[])
 {
-    constexpr double bx = K == 0 ? -0.5 : (K == 1 ? 0.5 : 0.0);
-    constexpr double by = K == 2 ? -0.5 : (K == 3 ? 0.5 : 0.0);
-    constexpr double bxx = K <= 1 ? 1.0 : 0.0;
-    constexpr double byy = K >= 2 ? 1.0 : 0.0;
-    d[0] = bx != 0.0 ? fma(bx, c, a[0]) : a[0];
-    d[1] = by != 0.0 ? fma(by, c, a[1]) : a[1];
-    d[2] = bxx != 0.0 ? a[2] + c : a[2];
-    d[3] = byy != 0.0 ? a[3] + c : a[3];
-    d[4] = a[4];
-    bd[0] = bx; bd[1] = by; bd[2] = bxx; bd[3] = byy; bd[4] = 0.0;
+    constexpr bool X = K <= 1;   // u_x moves (E/W) or u_y moves (S/N)
+    const double w0 = X ? d[0] : d[1];
+    const double o = X ? d[1] : d[0];
+    const double p = fma(o, o, 1.0);
+    e[0] = w0;
+    e[1] = p;
+    if constexpr (KIND == KIND_MEAN) {
+        // N = (1 + u_y^2) u_xx + (1 + u_x^2) u_yy - 2 u_x u_y u_xy with the moving
+        // second derivative (u_xx for E/W) equal to its value + c
+        const double mov2 = X ? d[2] : d[3], fix2 = X ? d[3] : d[2];
+        e[2] = fma(p, mov2, fix2);
+        e[3] = fix2;
+        e[4] = -2.0 * o * d[4];
+    } else {
+        e[2] = fma(d[2], d[3], -d[4] * d[4]);
+        e[3] = X ? d[3] : d[2];
+    }
 }
 
 template <int KIND, int K>
-__device__ __forceinline__ double edge_abs(const double a[5], double c)
+__device__ __forceinline__ double edge_abs(const double e[], double c)
 {
-    double d[5], bd[5];
-    edge_derivs<K>(a, c, d, bd);
-    Ring r;
-#pragma unroll
-    for (int t = 0; t < 5; ++t) { r.a[t] = d[t]; r.b[t] = bd[t]; }
-    return abs_kappa<KIND>(r, 0.0);
+    const double w = fma(EdgeSlope<K>::s, c, e[0]);
+    const double q = fma(w, w, e[1]);
+    const double rq = rsqrt_pos(q);
+    if (KIND == KIND_MEAN) {
+        const double num = fma(w, fma(e[3], w, e[4]), fma(e[1], c, e[2]));
+        return fabs(num) * (rq * rq * rq);
+    } else {
+        const double det = fma(e[3], c, e[2]);
+        const double r2 = rq * rq;
+        return fabs(det) * (r2 * r2);
+    }
 }
 
+// dq/dc = 2 s w = -+w;  mean: N' = p + s (2 A w + k);  Gaussian: D' = D1
 template <int KIND, int K>
-__device__ __forceinline__ double edge_dabs(const double a[5], double c)
+__device__ __forceinline__ double edge_dabs(const double e[], double c)
 {
-    double d[5], bd[5];
-    edge_derivs<K>(a, c, d, bd);
-    Ring r;
-#pragma unroll
-    for (int t = 0; t < 5; ++t) { r.a[t] = d[t]; r.b[t] = bd[t]; }
-    return dabs_kappa<KIND>(r, 0.0);
+    constexpr double s = EdgeSlope<K>::s;
+    const double w = fma(s, c, e[0]);
+    const double q = fma(w, w, e[1]);
+    const double rq = rsqrt_pos(q);
+    const double r2 = rq * rq;
+    if (KIND == KIND_MEAN) {
+        const double inner = fma(e[3], w, e[4]);
+        const double num = fma(w, inner, fma(e[1], c, e[2]));
+        const double dnum = fma(s, fma(e[3], w, inner), e[1]);
+        const double t = fma(-3.0 * s * num, w, dnum * q);   // N' q - 3/2 N q'
+        return signed_by(num, t * (r2 * r2 * rq));
+    } else {
+        const double det = fma(e[3], c, e[2]);
+        const double t = fma(-4.0 * s * det, w, e[3] * q);   // D' q - 2 D q'
+        return signed_by(det, t * (r2 * r2 * r2));
+    }
 }
 
 template <int KIND>
@@ -80,39 +110,49 @@ __device__ __forceinline__ void make_pixel_ring(const double w[5][5], PixelRing<
         double d[5];
         stencil_at(w, 2 + dys[k], 2 + dxs[k], d);
         const double q = fma(d[0], d[0], fma(d[1], d[1], 1.0));
-        if (KIND == KIND_MEAN) {
-            R.n0[k] = fma(fma(d[1], d[1], 1.0), d[2], fma(fma(d[0], d[0], 1.0), d[3], -2.0 * d[0] * d[1] * d[4]));
-            R.nc[k] = k == 0 ? -2.0 * (1.0 + q) : -0.5 * (double)(dys[k] * dxs[k]) * d[0] * d[1];
-            const double rq = rsqrt(q);
-            R.r[k] = rq * rq * rq;
-            R.m[k] = 0.0;
+        const double dd = (double)(dys[k] * dxs[k]);
+        if constexpr (KIND == KIND_MEAN) {
+            const double n0 = fma(fma(d[1], d[1], 1.0), d[2], fma(fma(d[0], d[0], 1.0), d[3], -2.0 * d[0] * d[1] * d[4]));
+            const double nc = k == 0 ? -2.0 * (1.0 + q) : -0.5 * dd * d[0] * d[1];
+            const double rq = rsqrt_pos(q);
+            const double r = rq * rq * rq;
+            R.g[k][0] = n0 * r;
+            R.g[k][1] = nc * r;
         } else {
-            const double iq = 1.0 / q;
-            R.r[k] = iq * iq;
-            if (k == 0) { R.n0[k] = d[2]; R.nc[k] = d[3]; R.m[k] = -d[4] * d[4]; }
-            else { R.n0[k] = d[2] * d[3]; R.nc[k] = d[4]; R.m[k] = (double)(dys[k] * dxs[k]); }
+            const double rq = rsqrt_pos(q);
+            const double r = (rq * rq) * (rq * rq);
+            const double det0 = fma(d[2], d[3], -d[4] * d[4]);
+            R.g[k][0] = det0 * r;
+            if (k == 0) {   // (u_xx - 2c)(u_yy - 2c) - u_xy^2
+                R.g[k][1] = -2.0 * (d[2] + d[3]) * r;
+                R.g[k][2] = 4.0 * r;
+            } else {        // u_xx u_yy - (u_xy + dy dx c / 4)^2
+                R.g[k][1] = -0.5 * dd * d[4] * r;
+                R.g[k][2] = -0.0625 * r;
+            }
         }
     }
-    stencil_at(w, 2, 3, R.e[0]);
-    stencil_at(w, 2, 1, R.e[1]);
-    stencil_at(w, 3, 2, R.e[2]);
-    stencil_at(w, 1, 2, R.e[3]);
+    double d[5];
+    stencil_at(w, 2, 3, d);
+    make_edge<KIND, 0>(d, R.e[0]);
+    stencil_at(w, 2, 1, d);
+    make_edge<KIND, 1>(d, R.e[1]);
+    stencil_at(w, 3, 2, d);
+    make_edge<KIND, 2>(d, R.e[2]);
+    stencil_at(w, 1, 2, d);
+    make_edge<KIND, 3>(d, R.e[3]);
 }
 
 template <int KIND>
 __device__ __forceinline__ double pixel_abs(const PixelRing<KIND>& R, double c)
 {
     double s = 0.0;
-    if (KIND == KIND_MEAN) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s += fabs(fma(R.nc[k], c, R.n0[k])) * R.r[k];
-    } else {
-        s += fabs(fma(R.n0[0] - 2.0 * c, R.nc[0] - 2.0 * c, R.m[0])) * R.r[0];
-#pragma unroll
-        for (int k = 1; k < 5; ++k) {
-            const double v = fma(0.25 * R.m[k], c, R.nc[k]);
-            s += fabs(fma(-v, v, R.n0[k])) * R.r[k];
-        }
+    for (int k = 0; k < 5; ++k) {
+        if constexpr (KIND == KIND_MEAN)
+            s += fabs(fma(R.g[k][1], c, R.g[k][0]));
+        else
+            s += fabs(fma(fma(R.g[k][2], c, R.g[k][1]), c, R.g[k][0]));
     }
     s += edge_abs<KIND, 0>(R.e[0], c);
     s += edge_abs<KIND, 1>(R.e[1], c);
@@ -125,26 +165,13 @@ template <int KIND>
 __device__ __forceinline__ double pixel_dabs(const PixelRing<KIND>& R, double c)
 {
     double s = 0.0;
-    if (KIND == KIND_MEAN) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const double n = fma(R.nc[k], c, R.n0[k]);
-            const double sg = n > 0.0 ? 1.0 : (n < 0.0 ? -1.0 : 0.0);
-            s += sg * R.nc[k] * R.r[k];
-        }
-    } else {
-        {
-            const double uxx = R.n0[0] - 2.0 * c, uyy = R.nc[0] - 2.0 * c;
-            const double det = fma(uxx, uyy, R.m[0]);
-            const double sg = det > 0.0 ? 1.0 : (det < 0.0 ? -1.0 : 0.0);
-            s += sg * (-2.0 * (uxx + uyy)) * R.r[0];
-        }
-#pragma unroll
-        for (int k = 1; k < 5; ++k) {
-            const double v = fma(0.25 * R.m[k], c, R.nc[k]);
-            const double det = fma(-v, v, R.n0[k]);
-            const double sg = det > 0.0 ? 1.0 : (det < 0.0 ? -1.0 : 0.0);
-            s += sg * (-0.5 * R.m[k] * v) * R.r[k];
+    for (int k = 0; k < 5; ++k) {
+        if constexpr (KIND == KIND_MEAN) {
+            s += signed_by(fma(R.g[k][1], c, R.g[k][0]), R.g[k][1]);
+        } else {
+            const double v = fma(fma(R.g[k][2], c, R.g[k][1]), c, R.g[k][0]);
+            s += signed_by(v, fma(R.g[k][2], c + c, R.g[k][1]));
         }
     }
     s += edge_dabs<KIND, 0>(R.e[0], c);
@@ -188,12 +215,15 @@ __device__ __forceinline__ void solve_cell(const T* __restrict__ uin, T* __restr
             auto Dpart = [&](double c) { return pixel_dabs<KIND>(R, c); };
             cval = local_solve(Kpart, Dpart, NoSum(), fs, alpha, M, G);
         } else {
-            Ring rg[9];
+            PolyRing<KIND> rg[9];
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-                for (int dx = -1; dx <= 1; ++dx)
-                    make_ring(uin, H, W, i + dy, j + dx, i, i + 1, j, j + 1, rg[(dy + 1) * 3 + dx + 1]);
+                for (int dx = -1; dx <= 1; ++dx) {
+                    Ring r;
+                    make_ring(uin, H, W, i + dy, j + dx, i, i + 1, j, j + 1, r);
+                    make_poly<KIND>(r, rg[(dy + 1) * 3 + dx + 1]);
+                }
             auto Kpart = [&](const auto& cs, auto& out) {
                 constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
@@ -201,12 +231,12 @@ __device__ __forceinline__ void solve_cell(const T* __restrict__ uin, T* __restr
 #pragma unroll
                 for (int t = 0; t < 9; ++t)
 #pragma unroll
-                    for (int k = 0; k < N; ++k) out[k] += abs_kappa<KIND>(rg[t], cs[k]);
+                    for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
             };
             auto Dpart = [&](double c) {
                 double acc = 0.0;
 #pragma unroll
-                for (int t = 0; t < 9; ++t) acc += dabs_kappa<KIND>(rg[t], c);
+                for (int t = 0; t < 9; ++t) acc += dabs_poly<KIND>(rg[t], c);
                 return acc;
             };
             cval = local_solve(Kpart, Dpart, NoSum(), fs, alpha, M, G);
@@ -262,19 +292,21 @@ __device__ __forceinline__ void solve_ring_cell(const T* __restrict__ uin, T* __
     const int j = NC * cc + colour % NC;
     double cval = 0.0;
     if (i < H && j < W) {   // uniform within the group
-        Ring rg;
+        Ring r;
         if (lane < 9)
-            make_ring(uin, H, W, i + lane / 3 - 1, j + lane % 3 - 1, i, i + 1, j, j + 1, rg);
+            make_ring(uin, H, W, i + lane / 3 - 1, j + lane % 3 - 1, i, i + 1, j, j + 1, r);
         else
-            zero_ring(rg);
+            zero_ring(r);
+        PolyRing<KIND> rg;
+        make_poly<KIND>(r, rg);
         const double fs = (double)f[(size_t)i * W + j] - (double)uin[(size_t)i * W + j];
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
-            for (int k = 0; k < N; ++k) out[k] = abs_kappa<KIND>(rg, cs[k]);
+            for (int k = 0; k < N; ++k) out[k] = abs_poly<KIND>(rg, cs[k]);
         };
-        auto Dpart = [&](double c) { return dabs_kappa<KIND>(rg, c); };
-        cval = local_solve(Kpart, Dpart, WaveSum<16>(), fs, alpha, M, G);
+        auto Dpart = [&](double c) { return dabs_poly<KIND>(rg, c); };
+        cval = local_solve(Kpart, Dpart, WaveSum<16, 2>(), fs, alpha, M, G);
     }
     if (lane < NC * NC) {
         const int ii = NC * cr + lane / NC, jj = NC * cc + lane % NC;
@@ -359,17 +391,19 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
 
     double cval;
     if (RPL > 0) {
-        Ring rg[RPL > 0 ? RPL : 1];
+        PolyRing<KIND> rg[RPL > 0 ? RPL : 1];
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int k = lane + t * GROUP;
+            Ring r;
             if (k < ncand) {
                 int i, j;
                 band_pixel(k, r0, r1, c0, c1, i, j);
-                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rg[t], ca.cpend, ca.nj, ca.lb);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, ca.lb);
             } else {
-                zero_ring(rg[t]);
+                zero_ring(r);
             }
+            make_poly<KIND>(r, rg[t]);
         }
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
@@ -378,12 +412,12 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
 #pragma unroll
             for (int t = 0; t < RPL; ++t)
 #pragma unroll
-                for (int k = 0; k < N; ++k) out[k] += abs_kappa<KIND>(rg[t], cs[k]);
+                for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
         };
         auto Dpart = [&](double c) {
             double acc = 0.0;
 #pragma unroll
-            for (int t = 0; t < RPL; ++t) acc += dabs_kappa<KIND>(rg[t], c);
+            for (int t = 0; t < RPL; ++t) acc += dabs_poly<KIND>(rg[t], c);
             return acc;
         };
         cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);
@@ -395,10 +429,12 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             for (int kk = lane; kk < ncand; kk += GROUP) {
                 int i, j;
                 Ring rr;
+                PolyRing<KIND> pr;
                 band_pixel(kk, r0, r1, c0, c1, i, j);
                 make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
+                make_poly<KIND>(rr, pr);
 #pragma unroll
-                for (int k = 0; k < N; ++k) out[k] += abs_kappa<KIND>(rr, cs[k]);
+                for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(pr, cs[k]);
             }
         };
         auto Dpart = [&](double c) {
@@ -406,9 +442,11 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             for (int kk = lane; kk < ncand; kk += GROUP) {
                 int i, j;
                 Ring rr;
+                PolyRing<KIND> pr;
                 band_pixel(kk, r0, r1, c0, c1, i, j);
                 make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
-                acc += dabs_kappa<KIND>(rr, c);
+                make_poly<KIND>(rr, pr);
+                acc += dabs_poly<KIND>(pr, c);
             }
             return acc;
         };
