@@ -222,18 +222,55 @@ __device__ __forceinline__ double abs_kappa_at(const T* __restrict__ u, int H, i
 
 // ---------------------------------------------------------------------------
 // Group sums.  Every lane of the group receives the bitwise identical total
-// (xor butterfly; IEEE addition is commutative), so all lanes of a group take
+// (butterfly; IEEE addition is commutative), so all lanes of a group take
 // identical branches in the local solver.  sum(x) reduces one value,
 // sum_n<N>(x) reduces N values with one synchronisation.
+//
+// Butterfly step OFF adds the value of a partner lane in the other half of an
+// aligned 2*OFF-lane group.  Inside a row of 16 lanes the partner value comes
+// through a DPP lane permutation (no LDS round trip): quad permutations for 1
+// and 2; for 4 and 8 the mirror inside 8 or 16 lanes, which pairs each lane with
+// one of the other half, and after the earlier steps every lane of a half holds
+// the same value, so the sum is the one xor 4 / xor 8 would give.  Across rows
+// (16, 32) the row-swap permutes exchange whole rows or half-waves.
 // ---------------------------------------------------------------------------
+template <int OFF>
+__device__ __forceinline__ double butterfly_step(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = (int)(unsigned)(v & 0xffffffffll), hi = (int)(v >> 32);
+    if constexpr (OFF < 16) {
+        constexpr int ctrl = OFF == 1 ? 0xB1 : OFF == 2 ? 0x4E : OFF == 4 ? 0x141 : 0x140;
+        const int plo = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xF, 0xF, false);
+        const int phi = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xF, 0xF, false);
+        return x + __hiloint2double(phi, plo);
+    } else {
+        // each swap returns the lane's own row (or half) and its partner's, in some order
+        auto sl = OFF == 16 ? __builtin_amdgcn_permlane16_swap((unsigned)lo, (unsigned)lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap((unsigned)lo, (unsigned)lo, false, false);
+        auto sh = OFF == 16 ? __builtin_amdgcn_permlane16_swap((unsigned)hi, (unsigned)hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap((unsigned)hi, (unsigned)hi, false, false);
+        return __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
+    }
+}
+
+template <int GROUP>
+__device__ __forceinline__ double butterfly(double x)
+{
+    if constexpr (GROUP > 1) x = butterfly_step<1>(x);
+    if constexpr (GROUP > 2) x = butterfly_step<2>(x);
+    if constexpr (GROUP > 4) x = butterfly_step<4>(x);
+    if constexpr (GROUP > 8) x = butterfly_step<8>(x);
+    if constexpr (GROUP > 16) x = butterfly_step<16>(x);
+    if constexpr (GROUP > 32) x = butterfly_step<32>(x);
+    return x;
+}
 template <int GROUP, int CHUNK_ = 8>
 struct WaveSum {
     static constexpr int CHUNK = CHUNK_;   // samples per fused reduction in local_solve
     __device__ __forceinline__ double operator()(double x) const
     {
-#pragma unroll
-        for (int off = 1; off < GROUP; off <<= 1) x += __shfl_xor(x, off, 64);
-        return x;
+        return butterfly<GROUP>(x);
     }
     template <int N>
     __device__ __forceinline__ void sum_n(double (&x)[N]) const
@@ -266,10 +303,7 @@ struct BlockSum {
         const int wave = threadIdx.x >> 6;
         double* slot = lds + parity * NW * NMAX;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) x[k] += __shfl_xor(x[k], off, 64);
-        }
+        for (int k = 0; k < N; ++k) x[k] = butterfly<64>(x[k]);
         if ((threadIdx.x & 63) == 0) {
 #pragma unroll
             for (int k = 0; k < N; ++k) slot[k * NW + wave] = x[k];
