@@ -268,10 +268,10 @@ static std::vector<BlockCfg> block_candidates(int b)
 {
     // the first entry is the single-image path's shape for this block side
     switch (b) {
-    case 2: return {{4, 4}, {16, 1}, {8, 2}, {2, 8}};
+    case 2: return {{2, 8}, {4, 4}, {16, 1}, {8, 2}};
     case 4: return {{8, 4}, {32, 1}, {16, 2}, {4, 8}};
-    case 8: return {{16, 4}, {64, 1}, {32, 2}, {8, 8}};
-    case 16: return {{32, 4}, {64, 2}, {16, 8}};
+    case 8: return {{32, 2}, {16, 4}, {64, 1}, {8, 8}};
+    case 16: return {{64, 2}, {32, 4}, {16, 8}};
     case 32: return {{64, 4}, {32, 8}};
     case 64: return {{256, 2}, {128, 4}, {64, 8}};
     case 128: return {{256, 4}, {512, 2}};

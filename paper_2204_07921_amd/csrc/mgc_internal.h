@@ -16,9 +16,10 @@ struct LaunchCtx {
 
 // Scratch of the coarse (lazily applied) levels.
 struct CoarseScratch {
-    double* partials;  // per block and row chunk: partial sums of f - u
-    int nchunk;        // set by launch_level_begin
-    double* cpend;     // pending corrections, m_j x n_j
+    double* partials;   // per block and row chunk: partial sums of f - u
+    int nchunk;         // set by launch_level_begin
+    double* cpend;      // pending corrections of the level being swept, m_j x n_j
+    double* cpend_alt;  // the previous coarse level's, while they are applied by the next level's sums pass
 };
 
 // b = 1: colour sweep from uin into uout (every pixel of uout is written).
@@ -29,7 +30,10 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
 // colours, the correction pass after them.
 bool level_is_lazy(int b);
 void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_per);
-hipError_t launch_level_begin(const LaunchCtx& L, const void* u, const void* f, int b, CoarseScratch& cs);
+// prev_b > 0: the coarse level of side prev_b left its corrections in cs.cpend
+// unapplied; this level's sums pass applies them to u (the same rounding as the
+// correction pass) before summing, so that level needs no correction pass of its own.
+hipError_t launch_level_begin(const LaunchCtx& L, void* u, const void* f, int b, CoarseScratch& cs, int prev_b = 0);
 hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScratch& cs);
 // F(u) into out[0] (device), using partials (energy_partials_count doubles).
 hipError_t launch_energy(const LaunchCtx& L, const void* u, const void* f, double* partials, double* out);

@@ -75,15 +75,21 @@ __global__ __launch_bounds__(GROUP > 64 ? GROUP : 256) void sweep_blocks_kernel(
 }
 
 // Coarse levels: partial sums of f - u, one workgroup per (block, chunk of rows).
-// partials[(p * nj + q) * nchunk + k] = sum over rows [r0 + k rows_per, ...) of block (p, q).
+// partials[(p * nj + q) * nchunk + k] = sum over rows [r0 + k rows_per, ...) of
+// block (p, q); the first chunk of each block also zeroes its pending correction.
+// With cprev set, the previous coarse level's pending corrections (block side
+// 2^lbp, njp blocks per row) are first added to u, rounded to the state type as
+// the correction pass would store them.
 template <typename T>
-__global__ __launch_bounds__(256) void block_sums_kernel(const T* __restrict__ u, const T* __restrict__ f, int H,
+__global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, const T* __restrict__ f, int H,
                                                          int W, int b, int nj, int nchunk, int rows_per,
-                                                         double* __restrict__ partials)
+                                                         double* __restrict__ partials, double* __restrict__ cpend,
+                                                         const double* __restrict__ cprev, int lbp, int njp)
 {
     __shared__ double lds[4];
     const int blk = blockIdx.x / nchunk, k = blockIdx.x - blk * nchunk;
     const int p = blk / nj, q = blk - p * nj;
+    if (k == 0 && threadIdx.x == 0) cpend[blk] = 0.0;
     const int c0 = q * b, c1 = min(c0 + b, W), w = c1 - c0;
     const int ra = p * b + k * rows_per;
     const int rb = min(min(ra + rows_per, (p + 1) * b), H);
@@ -92,18 +98,22 @@ __global__ __launch_bounds__(256) void block_sums_kernel(const T* __restrict__ u
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int i = ra + t / w, j = c0 + t % w;
         const size_t idx = (size_t)i * W + j;
-        acc += (double)f[idx] - (double)u[idx];
+        double v = (double)u[idx];
+        if (cprev) {
+            const double c = cprev[(size_t)(i >> lbp) * njp + (j >> lbp)];
+            if (c != 0.0) {
+                const T r = (T)(v + c);
+                u[idx] = r;
+                v = (double)r;
+            }
+        }
+        acc += (double)f[idx] - v;
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) partials[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
-}
-
-__global__ __launch_bounds__(256) void fill_kernel(double* __restrict__ x, size_t n, double v)
-{
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) x[t] = v;
 }
 
 // End of a coarse level: u <- u + c of the pixel's block (rounded to the state type).
@@ -212,10 +222,10 @@ static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, in
     // ring size of an unclipped block is 8b; shapes are the fastest of the batched autotuner's
     // candidates on the 1024x1024 and mixed-size workloads (fewer lanes, more records per lane)
     switch (b) {
-    case 2: return launch_blocks_cfg<T, KIND, 4, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 2: return launch_blocks_cfg<T, KIND, 2, 8, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 4: return launch_blocks_cfg<T, KIND, 8, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    case 8: return launch_blocks_cfg<T, KIND, 16, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    case 16: return launch_blocks_cfg<T, KIND, 32, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 8: return launch_blocks_cfg<T, KIND, 32, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 16: return launch_blocks_cfg<T, KIND, 64, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 32: return launch_blocks_cfg<T, KIND, 64, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 64: return launch_blocks_cfg<T, KIND, 256, 2, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 128: return launch_blocks_cfg<T, KIND, 256, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
@@ -243,7 +253,7 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
 void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_per)
 {
     const int mj = (H + b - 1) / b, nj = (W + b - 1) / b;
-    int rp = 16384 / b;              // about 16k pixels per chunk
+    int rp = 2048 / b;               // about 2k pixels per chunk: hundreds of workgroups per pass
     if (rp < 1) rp = 1;
     if (rp > b) rp = b;
     *rows_per = rp;
@@ -251,31 +261,43 @@ void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_p
     *nblocks = mj * nj;
 }
 
-hipError_t launch_level_begin(const LaunchCtx& L, const void* u, const void* f, int b, CoarseScratch& cs)
+static int log2i(int b)
+{
+    int lb = 0;
+    while ((1 << lb) < b) ++lb;
+    return lb;
+}
+
+hipError_t launch_level_begin(const LaunchCtx& L, void* u, const void* f, int b, CoarseScratch& cs, int prev_b)
 {
     int nblocks, nchunk, rows_per;
     coarse_geometry(L.H, L.W, b, &nblocks, &nchunk, &rows_per);
     cs.nchunk = nchunk;
     const int nj = (L.W + b - 1) / b;
+    const double* cprev = nullptr;
+    int lbp = 0, njp = 0;
+    if (prev_b > 0) {   // the previous level's corrections move to the other buffer and are applied here
+        double* t = cs.cpend;
+        cs.cpend = cs.cpend_alt;
+        cs.cpend_alt = t;
+        cprev = cs.cpend_alt;
+        lbp = log2i(prev_b);
+        njp = (L.W + prev_b - 1) / prev_b;
+    }
     dim3 grid((unsigned)nblocks * nchunk), block(256);
     if (L.f64)
-        hipLaunchKernelGGL(block_sums_kernel<double>, grid, block, 0, L.stream, (const double*)u, (const double*)f,
-                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials);
+        hipLaunchKernelGGL(block_sums_kernel<double>, grid, block, 0, L.stream, (double*)u, (const double*)f,
+                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials, cs.cpend, cprev, lbp, njp);
     else
-        hipLaunchKernelGGL(block_sums_kernel<float>, grid, block, 0, L.stream, (const float*)u, (const float*)f,
-                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t n = (size_t)nblocks;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.stream, cs.cpend, n, 0.0);
+        hipLaunchKernelGGL(block_sums_kernel<float>, grid, block, 0, L.stream, (float*)u, (const float*)f,
+                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials, cs.cpend, cprev, lbp, njp);
     return hipGetLastError();
 }
 
 hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScratch& cs)
 {
     const int nj = (L.W + b - 1) / b;
-    int lb = 0;
-    while ((1 << lb) < b) ++lb;
+    const int lb = log2i(b);
     const size_t n = (size_t)L.H * L.W;
     size_t g = (n + 255) / 256;
     if (g > 4096) g = 4096;

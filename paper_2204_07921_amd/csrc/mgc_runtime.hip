@@ -110,7 +110,7 @@ mg_status sweep(mg_curv_ctx* ctx, void* u, const void* f, int level, int colour)
 // scratch image (two-phase update); with an odd number of colours the result
 // is copied back into u.  Coarse levels take their block sums first and apply
 // the level's corrections after the last colour.
-mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level)
+mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level, int prev_b = 0, bool defer_end = false)
 {
     const mgc::LaunchCtx L = launch_ctx(ctx);
     hipError_t e;
@@ -131,21 +131,29 @@ mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level)
     }
     const int b = 1 << (level - 1);
     const bool lazy = mgc::level_is_lazy(b);
-    if (lazy && (e = mgc::launch_level_begin(L, u, f, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level begin");
+    if (lazy && (e = mgc::launch_level_begin(L, u, f, b, ctx->coarse, prev_b)) != hipSuccess)
+        return hip_fail(ctx, e, "level begin");
     for (int colour = 0; colour < 4; ++colour) {
         e = mgc::launch_sweep_blocks(L, u, f, b, colour, ctx->coarse);
         if (e != hipSuccess) return hip_fail(ctx, e, "block sweep launch");
     }
-    if (lazy && (e = mgc::launch_level_end(L, u, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level end");
+    if (lazy && !defer_end && (e = mgc::launch_level_end(L, u, b, ctx->coarse)) != hipSuccess)
+        return hip_fail(ctx, e, "level end");
     return MG_OK;
 }
 
 // All levels fine to coarse, all colours (one outer iteration of Algorithm 3).
 mg_status vcycle(mg_curv_ctx* ctx, void* u, const void* f)
 {
+    // a coarse level's corrections are applied by the next coarse level's sums pass;
+    // the coarsest level applies its own
+    int pending = 0;
     for (int level = 1; level <= ctx->J; ++level) {
-        mg_status st = level_sweeps(ctx, u, f, level);
+        const int b = 1 << (level - 1);
+        const bool defer = mgc::level_is_lazy(b) && level < ctx->J;
+        mg_status st = level_sweeps(ctx, u, f, level, pending, defer);
         if (st != MG_OK) return st;
+        pending = defer ? b : 0;
     }
     return MG_OK;
 }
@@ -211,7 +219,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->partials = nullptr;
     c->energy_dev = nullptr;
     c->energy_host = nullptr;
-    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr};
+    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
     const int np = mgc::energy_partials_count(p.height, p.width);
@@ -227,6 +235,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     if (hipMalloc(&c->pingpong, nb) != hipSuccess || hipMalloc((void**)&c->partials, sizeof(double) * np) != hipSuccess ||
         hipMalloc((void**)&c->coarse.partials, sizeof(double) * n_part) != hipSuccess ||
         hipMalloc((void**)&c->coarse.cpend, sizeof(double) * n_pend) != hipSuccess ||
+        hipMalloc((void**)&c->coarse.cpend_alt, sizeof(double) * n_pend) != hipSuccess ||
         hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         mg_curv_destroy(c);
@@ -334,6 +343,7 @@ void mg_curv_destroy(mg_curv_ctx* ctx)
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->coarse.partials) (void)hipFree(ctx->coarse.partials);
     if (ctx->coarse.cpend) (void)hipFree(ctx->coarse.cpend);
+    if (ctx->coarse.cpend_alt) (void)hipFree(ctx->coarse.cpend_alt);
     if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
     if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
     delete ctx;

@@ -320,31 +320,53 @@ __device__ __forceinline__ void solve_ring_cell(const T* __restrict__ uin, T* __
 }
 
 // ---------------------------------------------------------------------------
-// Ring candidates of block rows [r0, r1) x cols [c0, c1): the pixels of the box
-// [r0 - 1, r1] x [c0 - 1, c1] at distance <= 1 from the block's boundary.
+// Ring candidates of block rows [r0, r1) x cols [c0, c1) of an H x W image: the
+// pixels within distance 1 of a block side that does not lie on the image
+// border, as strips two pixels wide.  A side on the border has nothing outside
+// it, so its strip holds no ring pixel that the other strips miss.  The top and
+// bottom strips span the block's columns widened by one on each side (clipped to
+// the image), the left and right strips the rows between them.  For a block off
+// the border that is the whole (h + 2) x (w + 2) box less its interior, 8b pixels
+// for a b x b block; candidates whose taps all lie inside or all outside the
+// block get the zero record.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int band_count(int h, int w)
+struct RingBand {
+    int r0, r1, c0, c1;
+    int cl, wc;    // first column and width of the top and bottom strips
+    int ra;        // first row of the left and right strips
+    int nt, nb;    // pixels in the top and bottom strips (0 or 2 wc)
+    int per;       // pixels per row of the left and right strips (0, 2 or 4)
+    bool left;
+    int n;         // candidates in all
+};
+
+__host__ __device__ __forceinline__ RingBand ring_band(int H, int W, int r0, int r1, int c0, int c1)
 {
-    if (h <= 2 || w <= 2) return (h + 2) * (w + 2);
-    return 4 * (w + 2) + 4 * (h - 2);
+    RingBand B;
+    B.r0 = r0; B.r1 = r1; B.c0 = c0; B.c1 = c1;
+    const bool top = r0 > 0, bot = r1 < H, right = c1 < W;
+    B.left = c0 > 0;
+    B.cl = B.left ? c0 - 1 : c0;
+    B.wc = (right ? c1 : c1 - 1) - B.cl + 1;
+    B.ra = top ? r0 + 1 : r0;
+    const int rb = bot ? r1 - 2 : r1 - 1;   // last row of the side strips
+    const int hv = rb >= B.ra ? rb - B.ra + 1 : 0;
+    B.nt = top ? 2 * B.wc : 0;
+    B.nb = bot ? 2 * B.wc : 0;
+    B.per = 2 * ((B.left ? 1 : 0) + (right ? 1 : 0));
+    B.n = B.nt + B.nb + B.per * hv;
+    return B;
 }
 
-__device__ __forceinline__ void band_pixel(int k, int r0, int r1, int c0, int c1, int& i, int& j)
+__host__ __device__ __forceinline__ void band_at(const RingBand& B, int k, int& i, int& j)
 {
-    const int h = r1 - r0, w = c1 - c0, bw = w + 2;
-    if (h <= 2 || w <= 2) { i = r0 - 1 + k / bw; j = c0 - 1 + k % bw; return; }
-    const int top = 2 * bw, mid = 4 * (h - 2);
-    if (k < top) { i = r0 - 1 + k / bw; j = c0 - 1 + k % bw; return; }
-    k -= top;
-    if (k < mid) {
-        i = r0 + 1 + (k >> 2);
-        const int m = k & 3;
-        j = (m == 0) ? c0 - 1 : (m == 1) ? c0 : (m == 2) ? c1 - 1 : c1;
-        return;
-    }
-    k -= mid;
-    i = r1 - 1 + k / bw;
-    j = c0 - 1 + k % bw;
+    if (k < B.nt) { i = B.r0 - 1 + k / B.wc; j = B.cl + k % B.wc; return; }
+    k -= B.nt;
+    if (k < B.nb) { i = B.r1 - 1 + k / B.wc; j = B.cl + k % B.wc; return; }
+    k -= B.nb;
+    const int m = k & (B.per - 1);
+    i = B.ra + (B.per == 4 ? k >> 2 : k >> 1);
+    j = (B.left && m < 2) ? B.c0 - 1 + m : B.c1 - 1 + (m & 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,7 +409,8 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
     r = gsum(r);
     const double s = (double)h * (double)w;
     const double fs = r / s;
-    const int ncand = band_count(h, w);
+    const RingBand band = ring_band(H, W, r0, r1, c0, c1);
+    const int ncand = band.n;
 
     double cval;
     if (RPL > 0) {
@@ -398,7 +421,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             Ring r;
             if (k < ncand) {
                 int i, j;
-                band_pixel(k, r0, r1, c0, c1, i, j);
+                band_at(band, k, i, j);
                 make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, ca.lb);
             } else {
                 zero_ring(r);
@@ -409,15 +432,20 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
             for (int k = 0; k < N; ++k) out[k] = 0.0;
+            // slots past the last candidate hold zero records and are skipped
+            // (whole wavefronts at once on the coarse levels)
 #pragma unroll
             for (int t = 0; t < RPL; ++t)
+                if (lane + t * GROUP < ncand) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
+                    for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
+                }
         };
         auto Dpart = [&](double c) {
             double acc = 0.0;
 #pragma unroll
-            for (int t = 0; t < RPL; ++t) acc += dabs_poly<KIND>(rg[t], c);
+            for (int t = 0; t < RPL; ++t)
+                if (lane + t * GROUP < ncand) acc += dabs_poly<KIND>(rg[t], c);
             return acc;
         };
         cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);
@@ -430,7 +458,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
                 int i, j;
                 Ring rr;
                 PolyRing<KIND> pr;
-                band_pixel(kk, r0, r1, c0, c1, i, j);
+                band_at(band, kk, i, j);
                 make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
                 make_poly<KIND>(rr, pr);
 #pragma unroll
@@ -443,7 +471,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
                 int i, j;
                 Ring rr;
                 PolyRing<KIND> pr;
-                band_pixel(kk, r0, r1, c0, c1, i, j);
+                band_at(band, kk, i, j);
                 make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
                 make_poly<KIND>(rr, pr);
                 acc += dabs_poly<KIND>(pr, c);
