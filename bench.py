@@ -34,21 +34,22 @@ ALPHA = 20.0
 SIGMA = 0.1
 SEED = 0
 
-# FP64 operations (FMA = 2, rsqrt / reciprocal / abs-multiply = 1) that the pixel-level
-# kernel evaluates per solved interior pixel, counted from its formulas: the centre and the four
-# diagonal ring pixels have a constant q, so their curvature is linear (mean) or quadratic
-# (Gaussian) in c; the four edge neighbours use the full rational form with constant slopes.
-#   mean:     |K| evaluation 5 x 4 + 4 x 23 = 112,  derivative 5 x 5 + 4 x 38 = 177
-#   Gaussian: |K| evaluation 30 + 4 x 14 = 86,       derivative 45 + 4 x 22 = 133
+# FP64 operations (FMA = 2, add / multiply = 1; the hardware square-root estimate is not
+# counted, its refinement is) that the pixel-level kernel executes per solved interior pixel,
+# counted from its formulas.  The centre and the four diagonal ring pixels have a constant q, so
+# their curvature is a polynomial in c with the constant factor folded in; each of the four edge
+# neighbours evaluates N(c) (or D(c)) and q(c) from its moving first derivative w = w0 + s c and
+# a refined 1/sqrt(q) (8 flops):
+#   mean:     |K| evaluation 5 x 3 + 4 x 22 = 103,  derivative 5 x 4 + 4 x 32 = 148
+#   Gaussian: |K| evaluation 5 x 5 + 4 x 18 = 97,   derivative 5 x 9 + 4 x 24 = 141
 # Evaluations per pixel with M = 16 samples and G = 32 bisection steps: K(0), K(f*), 16 further
 # samples and K at the bisection point (19), and 32 derivatives.
-FLOPS_VALUE = {0: 112, 1: 86}
-FLOPS_DERIV = {0: 177, 1: 133}
+FLOPS_VALUE = {0: 103, 1: 97}
+FLOPS_DERIV = {0: 148, 1: 141}
 N_VALUE, N_DERIV = 19, 32
-# For reference, the general affine-record form of the same evaluations (all nine ring pixels
-# with runtime slopes) costs 9 x 30 and 9 x 60 (mean), 9 x 26 and 9 x 44 (Gaussian).
-FLOPS_VALUE_GENERAL = {0: 270, 1: 234}
-FLOPS_DERIV_GENERAL = {0: 540, 1: 396}
+# The survey's per-unit figure for the same work: about 40 (mean) or 30 (Gaussian) flops per
+# ring-pixel evaluation with general affine records, 9 ring pixels, 51 evaluations per pixel.
+FLOPS_SURVEY_PIXEL = {0: 9 * 51 * 40, 1: 9 * 51 * 30}
 FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
 
 
@@ -338,7 +339,7 @@ def main():
     avg_ms = ev0.elapsed_time(ev1) / launches
     pixels_per_launch = (H // 2) * (W // 2)
     flops_launch = pixels_per_launch * (N_VALUE * FLOPS_VALUE[args.kind] + N_DERIV * FLOPS_DERIV[args.kind])
-    flops_general = pixels_per_launch * (N_VALUE * FLOPS_VALUE_GENERAL[args.kind] + N_DERIV * FLOPS_DERIV_GENERAL[args.kind])
+    flops_survey = pixels_per_launch * FLOPS_SURVEY_PIXEL[args.kind]
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
 
     # per-level times (one V-cycle's share), for the report
@@ -392,7 +393,8 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "sweep_pixels_kernel (b = 1)", "avg_launch_ms": round(avg_ms, 5),
                      "flops_per_launch": flops_launch,
-                     "general_form_equivalent_tflops": round(flops_general / (avg_ms * 1e-3) / 1e12, 3),
+                     "flops_counted_as": "executed formula (FP64, interior-pixel form)",
+                     "survey_per_unit_tflops": round(flops_survey / (avg_ms * 1e-3) / 1e12, 3),
                      "note": "one launch = one colour of the pixel level (outer ring of cells on 16-lane "
                              "groups, interior cells one thread each), timed with HIP events on the library stream"},
         "level_ms": level_ms,

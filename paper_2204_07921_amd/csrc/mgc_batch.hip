@@ -272,8 +272,8 @@ static std::vector<BlockCfg> block_candidates(int b)
     case 4: return {{8, 4}, {32, 1}, {16, 2}, {4, 8}};
     case 8: return {{32, 2}, {16, 4}, {64, 1}, {8, 8}};
     case 16: return {{64, 2}, {32, 4}, {16, 8}};
-    case 32: return {{64, 4}, {32, 8}};
-    case 64: return {{256, 2}, {128, 4}, {64, 8}};
+    case 32: return {{256, 1}, {64, 4}, {32, 8}, {128, 2}};
+    case 64: return {{256, 2}, {128, 4}, {64, 8}, {512, 1}};
     case 128: return {{256, 4}, {512, 2}};
     case 256: return {{512, 4}, {1024, 2}};
     case 512: return {{512, 8}, {1024, 4}};
@@ -304,8 +304,8 @@ static hipError_t launch_batch_blocks(hipStream_t s, BlockCfg cfg, int grid, flo
     MGC_CASE(32, 1, false) MGC_CASE(16, 2, false) MGC_CASE(8, 4, false) MGC_CASE(4, 8, false)
     MGC_CASE(64, 1, false) MGC_CASE(32, 2, false) MGC_CASE(16, 4, false) MGC_CASE(8, 8, false)
     MGC_CASE(64, 2, false) MGC_CASE(32, 4, false) MGC_CASE(16, 8, false)
-    MGC_CASE(64, 4, false) MGC_CASE(32, 8, false)
-    MGC_CASE(256, 2, true) MGC_CASE(128, 4, true) MGC_CASE(64, 8, true)
+    MGC_CASE(64, 4, false) MGC_CASE(32, 8, false) MGC_CASE(128, 2, false) MGC_CASE(256, 1, false)
+    MGC_CASE(256, 2, true) MGC_CASE(128, 4, true) MGC_CASE(64, 8, true) MGC_CASE(512, 1, true)
     MGC_CASE(256, 4, true) MGC_CASE(512, 2, true)
     MGC_CASE(512, 4, true) MGC_CASE(1024, 2, true)
     MGC_CASE(512, 8, true) MGC_CASE(1024, 4, true)

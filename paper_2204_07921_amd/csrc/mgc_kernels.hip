@@ -219,14 +219,14 @@ template <typename T, int KIND>
 static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr,
                                   int nbc, const CoarseArgs& ca)
 {
-    // ring size of an unclipped block is 8b; shapes are the fastest of the batched autotuner's
-    // candidates on the 1024x1024 and mixed-size workloads (fewer lanes, more records per lane)
+    // ring size of an unclipped block is 8b (lanes x records per lane = 8b); per level the
+    // fastest of the batched autotuner's candidate shapes, timed on a 1024x1024 image
     switch (b) {
     case 2: return launch_blocks_cfg<T, KIND, 2, 8, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 4: return launch_blocks_cfg<T, KIND, 8, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 8: return launch_blocks_cfg<T, KIND, 32, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 16: return launch_blocks_cfg<T, KIND, 64, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    case 32: return launch_blocks_cfg<T, KIND, 64, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    case 32: return launch_blocks_cfg<T, KIND, 256, 1, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 64: return launch_blocks_cfg<T, KIND, 256, 2, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 128: return launch_blocks_cfg<T, KIND, 256, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 256: return launch_blocks_cfg<T, KIND, 512, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
