@@ -123,7 +123,7 @@ __device__ __forceinline__ void batch_block_item(float* __restrict__ u, const fl
     const int r0 = p * a.b, c0 = q * a.b;
     const int r1 = min(r0 + a.b, im.H), c1 = min(c0 + a.b, im.W);
     CoarseArgs ca{LAZY ? a.partials + a.part_off[img] : nullptr, a.nchunk, LAZY ? a.cpend + a.pend_off[img] : nullptr,
-                  nj, a.lb};
+                  nj, a.lb, nullptr, 8 * a.b};
     if (im.kind == 0)
         solve_block<float, 0, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
                                                 im.alpha, M, G, gs, ca);

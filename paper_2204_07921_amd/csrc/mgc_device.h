@@ -134,9 +134,32 @@ __device__ __forceinline__ double signed_by(double n, double v)
 // steps, and the record holds 7 (mean) or 6 (Gaussian) doubles instead of 10.
 template <int KIND>
 struct PolyRing {
+    static constexpr int NN = KIND == KIND_MEAN ? 4 : 3;
+    static constexpr int NCOEF = 3 + NN;
     double q0, q1, q2;
-    double n[KIND == KIND_MEAN ? 4 : 3];
+    double n[NN];
 };
+
+// Records kept in memory, coefficient-major: coefficient m of record k at reg[m * stride + k].
+template <int KIND>
+__device__ __forceinline__ void store_poly(double* __restrict__ reg, int stride, int k, const PolyRing<KIND>& p)
+{
+    reg[k] = p.q0;
+    reg[stride + k] = p.q1;
+    reg[2 * stride + k] = p.q2;
+#pragma unroll
+    for (int m = 0; m < PolyRing<KIND>::NN; ++m) reg[(3 + m) * stride + k] = p.n[m];
+}
+
+template <int KIND>
+__device__ __forceinline__ void load_poly(const double* __restrict__ reg, int stride, int k, PolyRing<KIND>& p)
+{
+    p.q0 = reg[k];
+    p.q1 = reg[stride + k];
+    p.q2 = reg[2 * stride + k];
+#pragma unroll
+    for (int m = 0; m < PolyRing<KIND>::NN; ++m) p.n[m] = reg[(3 + m) * stride + k];
+}
 
 template <int KIND>
 __device__ __forceinline__ void make_poly(const Ring& r, PolyRing<KIND>& p)

@@ -20,7 +20,15 @@ struct CoarseScratch {
     int nchunk;         // set by launch_level_begin
     double* cpend;      // pending corrections of the level being swept, m_j x n_j
     double* cpend_alt;  // the previous coarse level's, while they are applied by the next level's sums pass
+    double* rec;        // expanded ring records of the streamed levels (b >= STREAMED_B)
+    size_t rec_cap;     // doubles in rec
 };
+
+// Block side from which the ring no longer fits in registers (one workgroup per block, records
+// rebuilt from memory or read from the record scratch at every evaluation).
+constexpr int STREAMED_B = 1024;
+// Doubles of record scratch the streamed levels of an H x W image with J levels need.
+size_t record_scratch_doubles(int H, int W, int J);
 
 // b = 1: colour sweep from uin into uout (every pixel of uout is written).
 hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours);

@@ -70,7 +70,9 @@ __global__ __launch_bounds__(GROUP > 64 ? GROUP : 256) void sweep_blocks_kernel(
         const int r0 = p * b, c0 = q * b;
         const int r1 = min(r0 + b, H), c1 = min(c0 + b, W);
         BlockSum<GROUP> gs{lds, 0};
-        solve_block<T, KIND, GROUP, RPL, LAZY>(u, f, H, W, p, q, r0, r1, c0, c1, threadIdx.x, alpha, M, G, gs, ca);
+        CoarseArgs cb = ca;
+        if (cb.rec) cb.rec += (size_t)gid * PolyRing<KIND>::NCOEF * cb.rec_stride;   // this block's region
+        solve_block<T, KIND, GROUP, RPL, LAZY>(u, f, H, W, p, q, r0, r1, c0, c1, threadIdx.x, alpha, M, G, gs, cb);
     }
 }
 
@@ -231,19 +233,35 @@ static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, in
     case 128: return launch_blocks_cfg<T, KIND, 256, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 256: return launch_blocks_cfg<T, KIND, 512, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 512: return launch_blocks_cfg<T, KIND, 512, 8, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    default: return launch_blocks_cfg<T, KIND, 1024, 0, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
+    default: return launch_blocks_cfg<T, KIND, 1024, 0, true>(L, u, f, b, pr, pc, nbr, nbc, ca);   // b >= STREAMED_B
     }
 }
 
 bool level_is_lazy(int b) { return b >= 64; }
+
+size_t record_scratch_doubles(int H, int W, int J)
+{
+    size_t need = 0;
+    for (int level = 2; level <= J; ++level) {
+        const int b = 1 << (level - 1);
+        if (b < STREAMED_B) continue;
+        const size_t mj = (size_t)(H + b - 1) / b, nj = (size_t)(W + b - 1) / b;
+        const size_t per_colour = ((mj + 1) / 2) * ((nj + 1) / 2);   // colour 0 has the most blocks
+        const size_t n = per_colour * 7 * (size_t)(8 * b);
+        if (n > need) need = n;
+    }
+    return need;
+}
 
 hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, const CoarseScratch& cs)
 {
     const int pr = colour >> 1, pc = colour & 1;
     const int mj = (L.H + b - 1) / b, nj = (L.W + b - 1) / b;
     const int nbr = (mj - pr + 1) / 2, nbc = (nj - pc + 1) / 2;
-    CoarseArgs ca{cs.partials, cs.nchunk, cs.cpend, nj, 0};
+    CoarseArgs ca{cs.partials, cs.nchunk, cs.cpend, nj, 0, nullptr, 8 * b};
     while ((1 << ca.lb) < b) ++ca.lb;
+    // streamed levels keep their expanded records in memory when the scratch holds a region per block
+    if (b >= STREAMED_B && (size_t)nbr * nbc * 7 * (size_t)(8 * b) <= cs.rec_cap) ca.rec = cs.rec;
     if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)
                              : launch_blocks_t<double, 0>(L, u, f, b, pr, pc, nbr, nbc, ca);
     return L.kind ? launch_blocks_t<float, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)

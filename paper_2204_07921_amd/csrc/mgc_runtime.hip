@@ -219,7 +219,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->partials = nullptr;
     c->energy_dev = nullptr;
     c->energy_host = nullptr;
-    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr};
+    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
     const int np = mgc::energy_partials_count(p.height, p.width);
@@ -232,10 +232,13 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
         if ((size_t)nblocks * nchunk > n_part) n_part = (size_t)nblocks * nchunk;
         if ((size_t)nblocks > n_pend) n_pend = (size_t)nblocks;
     }
+    const size_t n_rec = mgc::record_scratch_doubles(p.height, p.width, c->J);
+    c->coarse.rec_cap = n_rec;
     if (hipMalloc(&c->pingpong, nb) != hipSuccess || hipMalloc((void**)&c->partials, sizeof(double) * np) != hipSuccess ||
         hipMalloc((void**)&c->coarse.partials, sizeof(double) * n_part) != hipSuccess ||
         hipMalloc((void**)&c->coarse.cpend, sizeof(double) * n_pend) != hipSuccess ||
         hipMalloc((void**)&c->coarse.cpend_alt, sizeof(double) * n_pend) != hipSuccess ||
+        (n_rec > 0 && hipMalloc((void**)&c->coarse.rec, sizeof(double) * n_rec) != hipSuccess) ||
         hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         mg_curv_destroy(c);
@@ -344,6 +347,7 @@ void mg_curv_destroy(mg_curv_ctx* ctx)
     if (ctx->coarse.partials) (void)hipFree(ctx->coarse.partials);
     if (ctx->coarse.cpend) (void)hipFree(ctx->coarse.cpend);
     if (ctx->coarse.cpend_alt) (void)hipFree(ctx->coarse.cpend_alt);
+    if (ctx->coarse.rec) (void)hipFree(ctx->coarse.rec);
     if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
     if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
     delete ctx;

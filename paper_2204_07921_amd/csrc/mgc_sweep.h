@@ -387,6 +387,8 @@ struct CoarseArgs {
     double* cpend;           // m_j x n_j pending corrections of this level
     int nj;
     int lb;                  // log2(b)
+    double* rec;             // RPL = 0: this block's region for its expanded ring records, or null
+    int rec_stride;          // records per coefficient row of a region (8b)
 };
 
 template <typename T, int KIND, int GROUP, int RPL, bool LAZY, class GSum>
@@ -446,6 +448,40 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
 #pragma unroll
             for (int t = 0; t < RPL; ++t)
                 if (lane + t * GROUP < ncand) acc += dabs_poly<KIND>(rg[t], c);
+            return acc;
+        };
+        cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);
+    } else if (ca.rec) {
+        // rings larger than the registers hold: each lane expands its records once into the
+        // block's region and reads them back (only its own) at every evaluation, in the same
+        // order as the rebuilding loop below
+        for (int kk = lane; kk < ncand; kk += GROUP) {
+            int i, j;
+            Ring rr;
+            PolyRing<KIND> pr;
+            band_at(band, kk, i, j);
+            make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
+            make_poly<KIND>(rr, pr);
+            store_poly<KIND>(ca.rec, ca.rec_stride, kk, pr);
+        }
+        auto Kpart = [&](const auto& cs, auto& out) {
+            constexpr int N = sizeof(out) / sizeof(double);
+#pragma unroll
+            for (int k = 0; k < N; ++k) out[k] = 0.0;
+            for (int kk = lane; kk < ncand; kk += GROUP) {
+                PolyRing<KIND> pr;
+                load_poly<KIND>(ca.rec, ca.rec_stride, kk, pr);
+#pragma unroll
+                for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(pr, cs[k]);
+            }
+        };
+        auto Dpart = [&](double c) {
+            double acc = 0.0;
+            for (int kk = lane; kk < ncand; kk += GROUP) {
+                PolyRing<KIND> pr;
+                load_poly<KIND>(ca.rec, ca.rec_stride, kk, pr);
+                acc += dabs_poly<KIND>(pr, c);
+            }
             return acc;
         };
         cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);

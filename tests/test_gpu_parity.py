@@ -262,6 +262,17 @@ def test_sampled_parity_1024_fp64(mg, orc):
     print(f"worst sampled error {worst:.3e}")
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("size,levels", [(4096, [1, 2, 7, 11, 12]), (8192, [1, 3, 10, 12, 13])])
+def test_sampled_parity_large_fp32(mg, orc, kind, size, levels):
+    """The large-scale configurations (4096^2 with J = 12 and 8192^2 with J = 13, sigma 0.1,
+    float32 state) in the benchmark's launch configuration: sampled blocks of one colour per level
+    against the oracle's local solve on the same state.  Levels with b >= 1024 run the
+    streamed-record path."""
+    worst = _sampled_check(mg, orc, size, size, kind, torch.float32, levels, 6, 1)
+    print(f"worst sampled error {worst:.3e}")
+
+
 def test_sampled_parity_streamed_coarse_blocks(mg, orc):
     """Blocks of side >= 1024 stream their ring from memory at every evaluation."""
     worst = _sampled_check(mg, orc, 1536, 1200, 0, torch.float32, [11, 9], 4, 1)
