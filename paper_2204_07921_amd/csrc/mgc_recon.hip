@@ -114,9 +114,12 @@ __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ u, 
 }
 
 // w = A v with v = sum over colour-k patches of pv_i phi_i (zero elsewhere and outside)
+// BS > 0: the patch side as a compile-time constant (the divisions by it become multiplications).
+template <int BS>
 __global__ __launch_bounds__(256) void blur_expand_kernel(const double* __restrict__ pv, int H, int W, ColourGrid cg,
                                                           Blur bl, double* __restrict__ w)
 {
+    const int b = BS > 0 ? BS : cg.b;
     REC_PIXELS {
         // patch row / column of the five rows and columns around (i, j), and whether they have colour k
         int prow[5], pcol[5];
@@ -126,8 +129,8 @@ __global__ __launch_bounds__(256) void blur_expand_kernel(const double* __restri
             const int ii = i + d - RB, jj = j + d - RB;
             rok[d] = ii >= 0 && ii < H;
             cok[d] = jj >= 0 && jj < W;
-            prow[d] = rok[d] ? ii / cg.b : 0;
-            pcol[d] = cok[d] ? jj / cg.b : 0;
+            prow[d] = rok[d] ? ii / b : 0;
+            pcol[d] = cok[d] ? jj / b : 0;
             rok[d] = rok[d] && (prow[d] & 1) == cg.pr;
             cok[d] = cok[d] && (pcol[d] & 1) == cg.pc;
         }
@@ -271,19 +274,22 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ w,
                                                    double* __restrict__ part_pq)
 {
     __shared__ double lds[4];
-    const int gid = (int)((blockIdx.x * blockDim.x + threadIdx.x) / G), lane = threadIdx.x % G;
-    const bool live = gid < cg.count();
+    constexpr int PER = 256 / G;   // lane groups per workgroup; the grid strides over the patches
+    const int lane = threadIdx.x % G, n = cg.count(), b = cg.b;
     double pq = 0.0;
-    int p = 0, q = 0;
-    if (live) patch_of(cg, gid, p, q);
-    const int b = cg.b;
-    const int r0 = p * b, r1 = live ? min(r0 + b, H) : r0, c0 = q * b, c1 = min(c0 + b, W);
-    const double s = patch_adjoint_sum<G>(w, H, W, bl, r0, r1, c0, c1, lane);
-    if (live && lane == 0) {
-        const size_t id = (size_t)p * cg.nj + q;
-        const double qi = s + 2.0 * alpha * pv[id];
-        qv[id] = qi;
-        pq = pv[id] * qi;
+    for (int g0 = blockIdx.x * PER; g0 < n; g0 += gridDim.x * PER) {
+        const int gid = g0 + threadIdx.x / G;
+        if (gid >= n) continue;   // whole lane groups
+        int p, q;
+        patch_of(cg, gid, p, q);
+        const int r0 = p * b, r1 = min(r0 + b, H), c0 = q * b, c1 = min(c0 + b, W);
+        const double s = patch_adjoint_sum<G>(w, H, W, bl, r0, r1, c0, c1, lane);
+        if (lane == 0) {
+            const size_t id = (size_t)p * cg.nj + q;
+            const double qi = s + 2.0 * alpha * pv[id];
+            qv[id] = qi;
+            pq += pv[id] * qi;
+        }
     }
     const double tot = block_total<256>(pq, lds);
     if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
@@ -301,15 +307,14 @@ __global__ __launch_bounds__(256) void update_xr_kernel(ColourGrid cg, const dou
     const double rr = scal[k_rr];
     const double a = pq > 0.0 ? rr / pq : 0.0;
     double acc = 0.0;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < cg.count()) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cg.count(); g += gridDim.x * blockDim.x) {
         int p, q;
         patch_of(cg, g, p, q);
         const size_t id = (size_t)p * cg.nj + q;
         x[id] += a * pv[id];
         const double rn = r[id] - a * qv[id];
         r[id] = rn;
-        acc = rn * rn;
+        acc += rn * rn;
     }
     const double tot = block_total<256>(acc, lds);
     if (threadIdx.x == 0) part_rr[blockIdx.x] = tot;
@@ -324,8 +329,7 @@ __global__ __launch_bounds__(256) void update_p_kernel(ColourGrid cg, const doub
     const double rn = sum_partials<256>(part_rr, npart, lds);
     const double ro = scal[k_old];
     const double beta = ro > 0.0 ? rn / ro : 0.0;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < cg.count()) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cg.count(); g += gridDim.x * blockDim.x) {
         int p, q;
         patch_of(cg, g, p, q);
         const size_t id = (size_t)p * cg.nj + q;
@@ -461,16 +465,17 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     if (n == 0) return MG_OK;
     const int G = lanes_for(bs);
     const int ng = groups_grid(n, G);        // workgroups of the patch-wise kernels
+    const int ngc = ng;                      // (the iteration's kernels stride, any grid is correct)
     const int nv = (n + 255) / 256;          // workgroups of the vector kernels
     const dim3 blk(256), gp = rec::pixel_grid(H, W);
     const int diagonal = bs >= 5;
     hipLaunchKernelGGL(rec::residual_kernel<T>, gp, blk, 0, st, (const T*)u, (const T*)b, H, W, c->blur, c->t);
 #define REC_G(KERNEL, ...)                                                                        \
     switch (G) {                                                                                  \
-    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(ng), blk, 0, st, __VA_ARGS__); break;           \
-    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(ng), blk, 0, st, __VA_ARGS__); break;           \
-    case 64: hipLaunchKernelGGL((KERNEL<64>), dim3(ng), blk, 0, st, __VA_ARGS__); break;         \
-    default: hipLaunchKernelGGL((KERNEL<256>), dim3(ng), blk, 0, st, __VA_ARGS__); break;        \
+    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;          \
+    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;          \
+    case 64: hipLaunchKernelGGL((KERNEL<64>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;        \
+    default: hipLaunchKernelGGL((KERNEL<256>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;       \
     }
     switch (G) {
     case 1: hipLaunchKernelGGL((rec::rhs_kernel<T, 1>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
@@ -481,9 +486,14 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     if (!diagonal) hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), blk, 0, st, (const double*)c->part_b, ng, c->scal, 0);
     for (int it = 0; it < (diagonal ? 0 : c->P.cg_iters); ++it) {
         const int k_old = it & 1, k_new = k_old ^ 1;
-        hipLaunchKernelGGL(rec::blur_expand_kernel, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
+        if (bs == 1)
+            hipLaunchKernelGGL(rec::blur_expand_kernel<1>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
+        else if (bs == 3)
+            hipLaunchKernelGGL(rec::blur_expand_kernel<3>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
+        else
+            hipLaunchKernelGGL(rec::blur_expand_kernel<0>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
         REC_G(rec::gram_kernel, (const double*)c->w, H, W, c->blur, cg, c->P.alpha, (const double*)c->pv, c->qv, c->part_a);
-        hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, ng,
+        hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, ngc,
                            (const double*)c->scal, k_old, c->x, c->r, (const double*)c->pv, (const double*)c->qv, c->part_b);
         hipLaunchKernelGGL(rec::update_p_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_b, nv, c->scal, k_old,
                            k_new, (const double*)c->r, c->pv);
