@@ -8,6 +8,15 @@ namespace fbs {
 
 constexpr double SQRT2 = 1.4142135623730951;
 
+// 1/sqrt(x) for finite x >= 1 (here x >= l^2 >= 1): the hardware estimate (relative error
+// about 2^-24) and one step of the series y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // Extremes of the normal curvatures d / ds^2 with the first plane index on ties.
 struct GcAcc {
     double kmin, dmin, kmax, dmax;
@@ -22,8 +31,8 @@ __device__ __forceinline__ void chord(double ua, double ub, double l, double l2,
     const double s = l2 + e * e;
     const double num = l * (h - uo);
     const double g0 = t0 - h, g1 = t1 - h;
-    d0 = num * rsqrt(s + g0 * g0);
-    d1 = num * rsqrt(s + g1 * g1);
+    d0 = num * rsqrt_pos(s + g0 * g0);
+    d1 = num * rsqrt_pos(s + g1 * g1);
     ds2 = s;
 }
 
