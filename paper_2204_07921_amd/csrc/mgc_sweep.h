@@ -397,20 +397,20 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
                                             double alpha, int M, int G, const GSum& gsum, const CoarseArgs& ca)
 {
     const int h = r1 - r0, w = c1 - c0;
-    double r = 0.0;
+    double rsum = 0.0;   // this lane's part of the sum of f - u over the block
     if (LAZY) {
         const double* part = ca.partials + ((size_t)p * ca.nj + q) * ca.nchunk;
-        for (int k = lane; k < ca.nchunk; k += GROUP) r += part[k];
+        for (int k = lane; k < ca.nchunk; k += GROUP) rsum += part[k];
     } else {
         for (int k = lane; k < h * w; k += GROUP) {
             const int i = r0 + k / w, j = c0 + k % w;
             const size_t idx = (size_t)i * W + j;
-            r += (double)f[idx] - (double)u[idx];
+            rsum += (double)f[idx] - (double)u[idx];
         }
     }
-    r = gsum(r);
+    // the group total of rsum (and with it f*) is taken after the ring records are built, so the
+    // loads of both are in flight together
     const double s = (double)h * (double)w;
-    const double fs = r / s;
     const RingBand band = ring_band(H, W, r0, r1, c0, c1);
     const int ncand = band.n;
 
@@ -430,6 +430,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             }
             make_poly<KIND>(r, rg[t]);
         }
+        const double fs = gsum(rsum) / s;
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
@@ -464,6 +465,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             make_poly<KIND>(rr, pr);
             store_poly<KIND>(ca.rec, ca.rec_stride, kk, pr);
         }
+        const double fs = gsum(rsum) / s;
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
@@ -486,6 +488,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
         };
         cval = local_solve(Kpart, Dpart, gsum, fs, alpha * s, M, G);
     } else {
+        const double fs = gsum(rsum) / s;
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
