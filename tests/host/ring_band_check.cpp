@@ -1,0 +1,59 @@
+// Host check of the block-ring enumeration used by the colour sweeps: for every block of every
+// image up to 23 x 23 and block sides 2..16, the candidates listed by ring_band / band_at lie
+// inside the image, are distinct, number at most 8b, and include every ring pixel, i.e. every
+// pixel whose nine clamped taps lie partly inside and partly outside the block (brute force).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <set>
+#include <utility>
+
+#include "../../paper_2204_07921_amd/csrc/mgc_sweep.h"
+
+static int clampi_h(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static bool is_ring(int H, int W, int i, int j, int r0, int r1, int c0, int c1)
+{
+    if (i < 0 || i >= H || j < 0 || j >= W) return false;
+    int n = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ci = clampi_h(i + dy, 0, H - 1), cj = clampi_h(j + dx, 0, W - 1);
+            n += (ci >= r0 && ci < r1 && cj >= c0 && cj < c1) ? 1 : 0;
+        }
+    return n > 0 && n < 9;
+}
+
+int main()
+{
+    long cases = 0, bad = 0;
+    for (int H = 1; H <= 23; ++H)
+        for (int W = 1; W <= 23; ++W)
+            for (int b = 2; b <= 16; b *= 2)
+                for (int r0 = 0; r0 < H; r0 += b)
+                    for (int c0 = 0; c0 < W; c0 += b) {
+                        const int r1 = r0 + b < H ? r0 + b : H, c1 = c0 + b < W ? c0 + b : W;
+                        const mgc::RingBand B = mgc::ring_band(H, W, r0, r1, c0, c1);
+                        std::set<std::pair<int, int>> got;
+                        bool dup = false, outside = false;
+                        for (int k = 0; k < B.n; ++k) {
+                            int i, j;
+                            mgc::band_at(B, k, i, j);
+                            outside = outside || i < 0 || i >= H || j < 0 || j >= W;
+                            dup = dup || !got.insert({i, j}).second;
+                        }
+                        bool cover = true;
+                        for (int i = r0 - 2; i <= r1 + 1; ++i)
+                            for (int j = c0 - 2; j <= c1 + 1; ++j)
+                                if (is_ring(H, W, i, j, r0, r1, c0, c1) && !got.count({i, j})) cover = false;
+                        ++cases;
+                        if (dup || outside || !cover || B.n > 8 * b) {
+                            if (bad < 5)
+                                std::printf("H %d W %d b %d block (%d, %d): n %d dup %d outside %d cover %d\n", H, W, b,
+                                            r0, c0, B.n, dup, outside, cover);
+                            ++bad;
+                        }
+                    }
+    std::printf("cases %ld bad %ld\n", cases, bad);
+    return bad == 0 ? 0 : 1;
+}
