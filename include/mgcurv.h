@@ -79,8 +79,11 @@ typedef struct mg_curv_ctx mg_curv_ctx;
 void mg_curv_default_params(mg_curv_params *p, int32_t height, int32_t width);
 
 /* Validate *params, bind the current HIP device and `hip_stream`
- * (a hipStream_t, may be NULL), and allocate the context's scratch (one
- * H x W ping-pong image for the pixel level and the energy partial sums).
+ * (a hipStream_t, may be NULL), and allocate the context's scratch: one
+ * H x W ping-pong image for the pixel level, the energy partial sums, the
+ * coarse levels' block sums and two arrays of pending corrections, and, when
+ * the levels reach blocks of side >= 1024, the expanded ring records of one
+ * colour's blocks (7 doubles per ring pixel; 7.3 MB at 8192 x 8192).
  * On success *out receives a context the caller releases with
  * mg_curv_destroy.  Errors: MG_E_INVALID / MG_E_SHAPE / MG_E_DTYPE for bad
  * parameters, MG_E_DEVICE without a GPU, MG_E_NOMEM. */
