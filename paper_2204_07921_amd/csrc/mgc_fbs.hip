@@ -224,19 +224,9 @@ __global__ __launch_bounds__(NT) void fbs_patch_level_kernel(const T* __restrict
                 ring_accumulate<KIND>(uo, v, (double)r, 8 * (r - 1), sum, acc);
                 double est;
                 if constexpr (KIND == 0) {
-#pragma unroll
-                    for (int off = 1; off < G; off <<= 1) sum += __shfl_xor(sum, off, 64);
-                    est = sum / (double)(8 * R);
+                    est = group_sum<G>(sum) / (double)(8 * R);
                 } else {
-#pragma unroll
-                    for (int off = 1; off < G; off <<= 1) {
-                        const double ok = __shfl_xor(acc.kmin, off, 64), od = __shfl_xor(acc.dmin, off, 64);
-                        const int oid = __shfl_xor(acc.imin, off, 64);
-                        if (ok < acc.kmin || (ok == acc.kmin && oid < acc.imin)) { acc.kmin = ok; acc.dmin = od; acc.imin = oid; }
-                        const double xk = __shfl_xor(acc.kmax, off, 64), xd = __shfl_xor(acc.dmax, off, 64);
-                        const int xid = __shfl_xor(acc.imax, off, 64);
-                        if (xk > acc.kmax || (xk == acc.kmax && xid < acc.imax)) { acc.kmax = xk; acc.dmax = xd; acc.imax = xid; }
-                    }
+                    group_extremes<G>(acc);
                     est = gc_choice(acc);
                 }
                 c = backward(c, c + est, eta * alpha * s, fs);

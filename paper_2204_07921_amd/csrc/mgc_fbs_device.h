@@ -17,6 +17,32 @@ __device__ __forceinline__ double rsqrt_pos(double x)
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// The value of lane (l xor OFF): a DPP quad permutation for OFF = 1 and 2 (no LDS
+// round trip), the LDS permute otherwise.
+template <int OFF>
+__device__ __forceinline__ int xlane_i(int x)
+{
+    if constexpr (OFF == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+    else if constexpr (OFF == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+    else return __shfl_xor(x, OFF, 64);
+}
+
+template <int OFF>
+__device__ __forceinline__ double xlane(double x)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = xlane_i<OFF>((int)(unsigned)(v & 0xffffffffll)), hi = xlane_i<OFF>((int)(v >> 32));
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over an aligned group of G lanes (xor butterfly, every lane gets the same total).
+template <int G, int OFF = 1>
+__device__ __forceinline__ double group_sum(double x)
+{
+    if constexpr (OFF >= G) return x;
+    else return group_sum<G, 2 * OFF>(x + xlane<OFF>(x));
+}
+
 // Extremes of the normal curvatures d / ds^2 with the first plane index on ties.
 struct GcAcc {
     double kmin, dmin, kmax, dmax;
@@ -63,6 +89,21 @@ __device__ __forceinline__ void ring_accumulate(double uo, const double (&v)[8],
             if (kap < g.kmin || (kap == g.kmin && idx < g.imin)) { g.kmin = kap; g.dmin = d[k]; g.imin = idx; }
             if (kap > g.kmax || (kap == g.kmax && idx < g.imax)) { g.kmax = kap; g.dmax = d[k]; g.imax = idx; }
         }
+    }
+}
+
+// Combine the extremes over an aligned group of G lanes (same rule as ring_accumulate).
+template <int G, int OFF = 1>
+__device__ __forceinline__ void group_extremes(GcAcc& acc)
+{
+    if constexpr (OFF < G) {
+        const double ok = xlane<OFF>(acc.kmin), od = xlane<OFF>(acc.dmin);
+        const int oid = xlane_i<OFF>(acc.imin);
+        if (ok < acc.kmin || (ok == acc.kmin && oid < acc.imin)) { acc.kmin = ok; acc.dmin = od; acc.imin = oid; }
+        const double xk = xlane<OFF>(acc.kmax), xd = xlane<OFF>(acc.dmax);
+        const int xid = xlane_i<OFF>(acc.imax);
+        if (xk > acc.kmax || (xk == acc.kmax && xid < acc.imax)) { acc.kmax = xk; acc.dmax = xd; acc.imax = xid; }
+        group_extremes<G, 2 * OFF>(acc);
     }
 }
 
