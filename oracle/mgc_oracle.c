@@ -21,7 +21,8 @@
  *    (reading R4), blocks clipped at the right and bottom edges;
  *  - the four-colour decomposition of Section 2.3 (colour of block (p, q) is
  *    2 (p mod 2) + (q mod 2), colours visited in the order 0, 1, 2, 3);
- *  - Algorithm 3: fine-to-coarse half V-cycle; inside each colour every block
+ *  - Algorithm 3: fine-to-coarse half V-cycle (or, with cycle = 1, the full
+ *    V-cycle that Section 2.2 compares it with: back again J-1..1); inside each colour every block
  *    B receives u <- u + c_B chi_B where c_B minimises the local energy
  *    F(u + c chi_B) (the arg min of the algorithm's inner step).  All c_B of
  *    one colour are computed from the state at the start of the colour and
@@ -62,6 +63,7 @@ typedef struct {
     int32_t bisections;    /* G */
     int32_t round_f32;     /* 1: round the state to float after each update */
     int32_t threads;       /* OpenMP threads for the per-colour block loop */
+    int32_t cycle;         /* 0: levels 1..J (the half V-cycle of Algorithm 3); 1: then J-1..1 */
 } orc_params;
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -391,14 +393,20 @@ int orc_sweep(const orc_params *P, double *u, const double *f, int level, int co
     return nblk;
 }
 
-/* One outer iteration of Algorithm 3: levels 1..J (fine to coarse), all colours. */
+static void orc_level(const orc_params *P, double *u, const double *f, int level)
+{
+    int ncol = orc_num_colours(P, level);
+    for (int colour = 0; colour < ncol; ++colour)
+        orc_sweep(P, u, f, level, colour, NULL);
+}
+
+/* One outer iteration of Algorithm 3: levels 1..J (fine to coarse), all colours;
+ * with cycle = 1 the levels J-1..1 follow (the full V-cycle of Section 2.2). */
 void orc_vcycle(const orc_params *P, double *u, const double *f)
 {
-    for (int level = 1; level <= P->levels; ++level) {
-        int ncol = orc_num_colours(P, level);
-        for (int colour = 0; colour < ncol; ++colour)
-            orc_sweep(P, u, f, level, colour, NULL);
-    }
+    for (int level = 1; level <= P->levels; ++level) orc_level(P, u, f, level);
+    if (P->cycle == 1)
+        for (int level = P->levels - 1; level >= 1; --level) orc_level(P, u, f, level);
 }
 
 /* Repeat V-cycles from the given u until |E_l - E_{l-1}| / |E_l| < rel_tol
@@ -420,5 +428,32 @@ int orc_solve(const orc_params *P, double *u, const double *f, double rel_tol, i
         if (rel_tol > 0.0 && (e == e_prev || fabs(e - e_prev) < rel_tol * fabs(e))) break;
         e_prev = e;
     }
+    return l;
+}
+
+/* As orc_solve with the stopping rule chosen: stop = 0 the relative energy change
+ * above; stop = 1 the relative change of the iterate, ||u_l - u_{l-1}||_2 <
+ * tol ||u_l||_2 (the rule of the paper's Tables 2-3, Section 4). */
+int orc_solve_rule(const orc_params *P, double *u, const double *f, double tol, int max_vcycles, int stop,
+                   double *energy_trace)
+{
+    if (stop == 0) return orc_solve(P, u, f, tol, max_vcycles, energy_trace);
+    const size_t n = (size_t)P->height * P->width;
+    double *prev = (double *)malloc(sizeof(double) * n);
+    if (energy_trace) energy_trace[0] = orc_energy(P->kind, u, f, P->height, P->width, P->alpha);
+    int l = 0;
+    while (l < max_vcycles) {
+        memcpy(prev, u, sizeof(double) * n);
+        orc_vcycle(P, u, f);
+        ++l;
+        if (energy_trace) energy_trace[l] = orc_energy(P->kind, u, f, P->height, P->width, P->alpha);
+        double num = 0.0, den = 0.0;
+        for (size_t k = 0; k < n; ++k) {
+            num += (u[k] - prev[k]) * (u[k] - prev[k]);
+            den += u[k] * u[k];
+        }
+        if (tol > 0.0 && sqrt(num) < tol * sqrt(den)) break;
+    }
+    free(prev);
     return l;
 }

@@ -38,7 +38,7 @@ class OracleParams(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
                 ("kind", C.c_int32), ("levels", C.c_int32), ("fine_colours", C.c_int32),
                 ("samples", C.c_int32), ("bisections", C.c_int32), ("round_f32", C.c_int32),
-                ("threads", C.c_int32)]
+                ("threads", C.c_int32), ("cycle", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -89,6 +89,8 @@ def _load():
         L.orc_vcycle.argtypes = [P, _DP, _DP]
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [P, _DP, _DP, C.c_double, C.c_int, C.c_void_p]
+        L.orc_solve_rule.restype = C.c_int
+        L.orc_solve_rule.argtypes = [P, _DP, _DP, C.c_double, C.c_int, C.c_int, C.c_void_p]
         L.orc_num_colours.restype = C.c_int
         L.orc_num_colours.argtypes = [P, C.c_int]
         FP = C.POINTER(FbsParams)
@@ -139,11 +141,11 @@ class Oracle:
 
     def __init__(self, height: int, width: int, alpha: float, kind: int = 0, levels: int = 0,
                  fine_colours: int = 4, samples: int = 16, bisections: int = 32,
-                 round_f32: bool = False, threads: int = 1):
+                 round_f32: bool = False, threads: int = 1, cycle: int = 0):
         if levels <= 0:
             levels = default_levels(height, width)
         self.p = OracleParams(height, width, float(alpha), kind, levels, fine_colours,
-                              samples, bisections, int(bool(round_f32)), threads)
+                              samples, bisections, int(bool(round_f32)), threads, int(cycle))
         self.L = _load()
 
     # geometry -------------------------------------------------------------
@@ -218,6 +220,14 @@ class Oracle:
         assert u.dtype == np.float64 and u.flags.c_contiguous
         trace = np.zeros(max_vcycles + 1)
         n = self.L.orc_solve(C.byref(self.p), u, _f64(f), rel_tol, max_vcycles, trace.ctypes.data)
+        return n, trace[: n + 1].copy()
+
+    def solve_rule(self, u: np.ndarray, f, tol: float, max_vcycles: int = 1000, stop: int = 0):
+        """In-place solve with stop 0 (relative energy change) or 1 (relative change of u);
+        returns (vcycles_done, energy trace E_0..E_done)."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        trace = np.zeros(max_vcycles + 1)
+        n = self.L.orc_solve_rule(C.byref(self.p), u, _f64(f), tol, max_vcycles, stop, trace.ctypes.data)
         return n, trace[: n + 1].copy()
 
     def energy(self, u, f) -> float:

@@ -329,3 +329,55 @@ def test_accept_rule_rejects_worse_candidates(orc):
             E1 = coarse.energy(u, f)
             assert E1 <= E0 + 1e-10 * E0
             E0 = E1
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_full_cycle_monotone_and_fixed_point(orc, kind):
+    """Full V-cycle (Section 2.2: fine to coarse, then back to the finest level): with nine fine
+    colours every sweep is non-increasing, so one full cycle ends at or below the half cycle it
+    starts with; a constant image stays bitwise fixed; with J = 1 there is nothing to go back
+    through and the two cycles agree bitwise."""
+    H, W = 26, 21
+    f, _ = noisy_image(H, W, 5, 0.08)
+    half = orc.Oracle(H, W, 20.0, kind, fine_colours=9)
+    full = orc.Oracle(H, W, 20.0, kind, fine_colours=9, cycle=1)
+    uh, uf = f.copy(), f.copy()
+    half.vcycle(uh, f)
+    full.vcycle(uf, f)
+    assert full.energy(uf, f) <= half.energy(uh, f) + 1e-10 * (1 + half.energy(uh, f))
+    assert not np.array_equal(uh, uf)
+    c = np.full((H, W), 0.375)
+    u = c.copy()
+    full.vcycle(u, c)
+    assert np.array_equal(u, c)
+    one_h = orc.Oracle(H, W, 20.0, kind, levels=1)
+    one_f = orc.Oracle(H, W, 20.0, kind, levels=1, cycle=1)
+    a, b = f.copy(), f.copy()
+    one_h.vcycle(a, f)
+    one_f.vcycle(b, f)
+    assert np.array_equal(a, b)
+
+
+def test_relerr_stop_rule_is_the_first_small_step(orc):
+    """The relErr(u) rule of Section 4 (||u_l - u_{l-1}|| < tol ||u_l||) stops at the first V-cycle
+    whose step is small: replayed cycle by cycle, with the norms taken by numpy."""
+    H, W = 30, 27
+    f, _ = noisy_image(H, W, 8, 0.1)
+    for cycle in (0, 1):
+        o = orc.Oracle(H, W, 20.0, 0, cycle=cycle)
+        tol = 3e-3
+        u = f.copy()
+        n, trace = o.solve_rule(u, f, tol, max_vcycles=60, stop=1)
+        assert 1 <= n < 60 and len(trace) == n + 1
+        v = f.copy()
+        for l in range(1, n + 1):
+            prev = v.copy()
+            o.vcycle(v, f)
+            small = np.linalg.norm(v - prev) < tol * np.linalg.norm(v)
+            assert small == (l == n), (cycle, l, n)
+        assert np.array_equal(u, v)
+    # a constant image does not move: relErr = 0 after the first cycle
+    c = np.full((H, W), 0.5)
+    o = orc.Oracle(H, W, 20.0, 1)
+    n, _ = o.solve_rule(c.copy(), c, 1e-9, max_vcycles=10, stop=1)
+    assert n == 1
