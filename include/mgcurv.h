@@ -59,6 +59,12 @@ typedef enum {
 typedef enum { MG_CURV_MEAN = 0, MG_CURV_GAUSS = 1 } mg_curv_kind;
 typedef enum { MG_F32 = 0, MG_F64 = 1 } mg_dtype;
 
+/* Stopping rules of the solves (Section 4). */
+typedef enum {
+    MG_STOP_ENERGY = 0,   /* |E_l - E_{l-1}| < tol |E_l| (Section 4) */
+    MG_STOP_RELERR_U = 1  /* ||u_l - u_{l-1}||_2 < tol ||u_l||_2 (Section 4, relErr(u)) */
+} mg_stop_rule;
+
 typedef struct {
     int32_t height;        /* H >= 2 */
     int32_t width;         /* W >= 2 */
@@ -70,12 +76,16 @@ typedef struct {
                               (3 x 3 pattern; pixels of one colour then share no ring pixel) */
     int32_t samples;       /* M, even, 2..256 (default 16) */
     int32_t bisections;    /* G, 0..64 (default 32) */
+    int32_t cycle;         /* 0: levels 1..J, the half V-cycle of Algorithm 3 (default);
+                              1: then J-1..1, the full V-cycle Section 2.2 compares it with.
+                              Batches take 0 only. */
 } mg_curv_params;
 
 typedef struct mg_curv_ctx mg_curv_ctx;
 
 /* Fill *p with the defaults for an H x W image: alpha 20, mean curvature,
- * levels 0 (automatic), float state, 4 fine colours, M = 16, G = 32. */
+ * levels 0 (automatic), float state, 4 fine colours, M = 16, G = 32, half
+ * V-cycle. */
 void mg_curv_default_params(mg_curv_params *p, int32_t height, int32_t width);
 
 /* Validate *params, bind the current HIP device and `hip_stream`
@@ -105,6 +115,17 @@ mg_status mg_curv_vcycle(mg_curv_ctx *ctx, void *u, const void *f, double *energ
  * error; MG_E_NONFINITE if F(u) on entry is not finite (u untouched). */
 mg_status mg_curv_solve(mg_curv_ctx *ctx, void *u, const void *f, double rel_tol, int32_t max_vcycles,
                         int32_t *vcycles_done, double *final_energy, double *energy_trace);
+
+/* As mg_curv_solve with the stopping rule chosen (mg_stop_rule): with
+ * MG_STOP_ENERGY exactly mg_curv_solve; with MG_STOP_RELERR_U V-cycles run
+ * until ||u_l - u_{l-1}||_2 < tol ||u_l||_2 (norms in FP64; tol <= 0 runs
+ * exactly max_vcycles).  The iterate rule keeps a copy of the previous u,
+ * which the context allocates on the first such call (MG_E_NOMEM if that
+ * fails).  Returns MG_OK, MG_NOT_CONVERGED, MG_E_INVALID for an unknown rule,
+ * or the errors of mg_curv_solve.  Outputs nullable; *final_energy is F(u)
+ * at the end. */
+mg_status mg_curv_solve_rule(mg_curv_ctx *ctx, void *u, const void *f, int32_t stop, double tol, int32_t max_vcycles,
+                             int32_t *vcycles_done, double *final_energy);
 
 /* Run V-cycles on u until F(u) <= target_energy (checked before the first
  * cycle as well) or max_vcycles cycles have run: the refinement step of a
@@ -288,11 +309,6 @@ typedef struct {
     int32_t cycle;        /* 0: levels 1..J (half V-cycle), 1: then J-1..1 (full V-cycle) */
     int32_t reserved;     /* must be 0 */
 } mg_fbs_params;
-
-typedef enum {
-    MG_STOP_ENERGY = 0,   /* |E_l - E_{l-1}| < tol |E_l| (Section 4) */
-    MG_STOP_RELERR_U = 1  /* ||u_l - u_{l-1}||_2 < tol ||u_l||_2 (Section 4, relErr(u)) */
-} mg_stop_rule;
 
 typedef struct mg_fbs_ctx mg_fbs_ctx;
 

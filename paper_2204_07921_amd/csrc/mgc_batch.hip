@@ -561,6 +561,7 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
         if (p.curvature != MG_CURV_MEAN && p.curvature != MG_CURV_GAUSS) return bfail(nullptr, MG_E_INVALID, "image %d: bad curvature", i);
         if (p.state_dtype != MG_F32) return bfail(nullptr, MG_E_DTYPE, "batched images use float32 state");
         if (p.fine_colours != 4) return bfail(nullptr, MG_E_INVALID, "batched images use four fine colours");
+        if (p.cycle != 0) return bfail(nullptr, MG_E_INVALID, "batched images use the half V-cycle");
         if (p.samples != p0.samples || p.bisections != p0.bisections)
             return bfail(nullptr, MG_E_INVALID, "samples and bisections must be equal across the batch");
         if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return bfail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");

@@ -43,6 +43,9 @@ void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_p
 // correction pass) before summing, so that level needs no correction pass of its own.
 hipError_t launch_level_begin(const LaunchCtx& L, void* u, const void* f, int b, CoarseScratch& cs, int prev_b = 0);
 hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScratch& cs);
+// out[0] = ||u - prev||^2, out[1] = ||u||^2 (device, FP64, fixed order), using
+// partials (2 x energy_partials_count doubles).
+hipError_t launch_diff_norms(const LaunchCtx& L, const void* u, const void* prev, double* partials, double* out);
 // F(u) into out[0] (device), using partials (energy_partials_count doubles).
 hipError_t launch_energy(const LaunchCtx& L, const void* u, const void* f, double* partials, double* out);
 int energy_partials_count(int H, int W);

@@ -154,6 +154,34 @@ __global__ __launch_bounds__(256) void energy_partial_kernel(const T* __restrict
     if (threadIdx.x == 0) partials[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
+// Partial sums of (u - prev)^2 (partials[0 .. gridDim)) and u^2 (partials[gridDim ..)).
+template <typename T>
+__global__ __launch_bounds__(256) void diff_norms_kernel(const T* __restrict__ u, const T* __restrict__ prev,
+                                                         size_t n, double* __restrict__ partials)
+{
+    __shared__ double lds[8];
+    double a = 0.0, b = 0.0;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const double x = (double)u[p], d = x - (double)prev[p];
+        a += d * d;
+        b += x * x;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        lds[threadIdx.x >> 6] = a;
+        lds[4 + (threadIdx.x >> 6)] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+        partials[gridDim.x + blockIdx.x] = (lds[4] + lds[5]) + (lds[6] + lds[7]);
+    }
+}
+
 __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partials, int n,
                                                            double* __restrict__ out)
 {
@@ -325,6 +353,23 @@ hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScra
     else
         hipLaunchKernelGGL(apply_level_kernel<float>, dim3((unsigned)g), dim3(256), 0, L.stream, (float*)u, L.H, L.W,
                            lb, nj, (const double*)cs.cpend);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_norms(const LaunchCtx& L, const void* u, const void* prev, double* partials, double* out)
+{
+    const int np = energy_partials_count(L.H, L.W);
+    const size_t n = (size_t)L.H * L.W;
+    if (L.f64)
+        hipLaunchKernelGGL(diff_norms_kernel<double>, dim3(np), dim3(256), 0, L.stream, (const double*)u,
+                           (const double*)prev, n, partials);
+    else
+        hipLaunchKernelGGL(diff_norms_kernel<float>, dim3(np), dim3(256), 0, L.stream, (const float*)u,
+                           (const float*)prev, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, L.stream, partials, np, out);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, L.stream, partials + np, np, out + 1);
     return hipGetLastError();
 }
 

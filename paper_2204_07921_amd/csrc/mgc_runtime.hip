@@ -23,6 +23,10 @@ struct mg_curv_ctx {
     mgc::CoarseScratch coarse;  // block sums and pending corrections of the coarse levels
     double* energy_dev;    // one double
     double* energy_host;   // pinned host double
+    void* prev;            // previous iterate for the relErr(u) rule (allocated on first use)
+    double* norm_part;     // 2 x energy_partials_count partial sums of ||u - prev||^2 and ||u||^2
+    double* norm_dev;      // the two sums
+    double* norm_host;     // pinned host copy of the two sums
     std::string err;
 };
 
@@ -145,12 +149,18 @@ mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level, int 
 // All levels fine to coarse, all colours (one outer iteration of Algorithm 3).
 mg_status vcycle(mg_curv_ctx* ctx, void* u, const void* f)
 {
-    // a coarse level's corrections are applied by the next coarse level's sums pass;
-    // the coarsest level applies its own
+    // levels 1..J, and with the full cycle J-1..1 after them; a coarse level's
+    // corrections are applied by the sums pass of the next level in this order when
+    // that level is coarse too, otherwise by the level's own correction pass
+    int order[2 * 32];
+    int n = 0;
+    for (int level = 1; level <= ctx->J; ++level) order[n++] = level;
+    if (ctx->P.cycle == 1)
+        for (int level = ctx->J - 1; level >= 1; --level) order[n++] = level;
     int pending = 0;
-    for (int level = 1; level <= ctx->J; ++level) {
-        const int b = 1 << (level - 1);
-        const bool defer = mgc::level_is_lazy(b) && level < ctx->J;
+    for (int k = 0; k < n; ++k) {
+        const int level = order[k], b = 1 << (level - 1);
+        const bool defer = mgc::level_is_lazy(b) && k + 1 < n && mgc::level_is_lazy(1 << (order[k + 1] - 1));
         mg_status st = level_sweeps(ctx, u, f, level, pending, defer);
         if (st != MG_OK) return st;
         pending = defer ? b : 0;
@@ -188,6 +198,7 @@ void mg_curv_default_params(mg_curv_params* p, int32_t height, int32_t width)
     p->fine_colours = 4;
     p->samples = 16;
     p->bisections = 32;
+    p->cycle = 0;
 }
 
 mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_ctx** out)
@@ -204,6 +215,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     if (p.fine_colours != 4 && p.fine_colours != 9) return fail(nullptr, MG_E_INVALID, "fine_colours must be 4 or 9");
     if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return fail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");
     if (p.bisections < 0 || p.bisections > 64) return fail(nullptr, MG_E_INVALID, "bisections must be in [0, 64]");
+    if (p.cycle != 0 && p.cycle != 1) return fail(nullptr, MG_E_INVALID, "cycle must be 0 (half) or 1 (full)");
     const int Jmax = auto_levels(p.height, p.width) + 1;
     if (p.levels < 0 || p.levels > Jmax) return fail(nullptr, MG_E_INVALID, "levels must be in [0, %d]", Jmax);
 
@@ -219,6 +231,10 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->partials = nullptr;
     c->energy_dev = nullptr;
     c->energy_host = nullptr;
+    c->prev = nullptr;
+    c->norm_part = nullptr;
+    c->norm_dev = nullptr;
+    c->norm_host = nullptr;
     c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
@@ -314,6 +330,52 @@ mg_status mg_curv_solve(mg_curv_ctx* ctx, void* u, const void* f, double rel_tol
     return (rel_tol > 0.0 && !converged) ? MG_NOT_CONVERGED : MG_OK;
 }
 
+mg_status mg_curv_solve_rule(mg_curv_ctx* ctx, void* u, const void* f, int32_t stop, double tol, int32_t max_vcycles,
+                             int32_t* vcycles_done, double* final_energy)
+{
+    if (stop == MG_STOP_ENERGY) return mg_curv_solve(ctx, u, f, tol, max_vcycles, vcycles_done, final_energy, nullptr);
+    mg_status st = check_buffers(ctx, u, f);
+    if (st != MG_OK) return st;
+    if (stop != MG_STOP_RELERR_U) return fail(ctx, MG_E_INVALID, "unknown stopping rule %d", stop);
+    if (max_vcycles < 0) return fail(ctx, MG_E_INVALID, "max_vcycles must be >= 0");
+    if (!std::isfinite(tol)) return fail(ctx, MG_E_INVALID, "tol must be finite");
+    double e;
+    st = energy(ctx, u, f, &e);
+    if (st != MG_OK) return st;
+    if (!std::isfinite(e)) return fail(ctx, MG_E_NONFINITE, "energy of the initial state is not finite");
+    const int np = mgc::energy_partials_count(ctx->P.height, ctx->P.width);
+    if (!ctx->prev) {
+        if (hipMalloc(&ctx->prev, state_bytes(ctx)) != hipSuccess ||
+            hipMalloc((void**)&ctx->norm_part, sizeof(double) * 2 * np) != hipSuccess ||
+            hipMalloc((void**)&ctx->norm_dev, sizeof(double) * 2) != hipSuccess ||
+            hipHostMalloc((void**)&ctx->norm_host, sizeof(double) * 2, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, MG_E_NOMEM, "allocation of the previous-iterate buffer failed");
+        }
+    }
+    const mgc::LaunchCtx L = launch_ctx(ctx);
+    int done = 0;
+    bool converged = false;
+    while (done < max_vcycles) {
+        hipError_t he = hipMemcpyAsync(ctx->prev, u, state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
+        if (he != hipSuccess) return hip_fail(ctx, he, "previous-iterate copy");
+        st = vcycle(ctx, u, f);
+        if (st != MG_OK) return st;
+        ++done;
+        he = mgc::launch_diff_norms(L, u, ctx->prev, ctx->norm_part, ctx->norm_dev);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(ctx->norm_host, ctx->norm_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) return hip_fail(ctx, he, "relErr(u) norms");
+        if (tol > 0.0 && std::sqrt(ctx->norm_host[0]) < tol * std::sqrt(ctx->norm_host[1])) { converged = true; break; }
+    }
+    st = energy(ctx, u, f, &e);
+    if (st != MG_OK) return st;
+    if (vcycles_done) *vcycles_done = done;
+    if (final_energy) *final_energy = e;
+    return (tol > 0.0 && !converged) ? MG_NOT_CONVERGED : MG_OK;
+}
+
 mg_status mg_curv_solve_target(mg_curv_ctx* ctx, void* u, const void* f, double target_energy, int32_t max_vcycles,
                                int32_t* vcycles_done, double* final_energy)
 {
@@ -350,6 +412,10 @@ void mg_curv_destroy(mg_curv_ctx* ctx)
     if (ctx->coarse.rec) (void)hipFree(ctx->coarse.rec);
     if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
     if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
+    if (ctx->prev) (void)hipFree(ctx->prev);
+    if (ctx->norm_part) (void)hipFree(ctx->norm_part);
+    if (ctx->norm_dev) (void)hipFree(ctx->norm_dev);
+    if (ctx->norm_host) (void)hipHostFree(ctx->norm_host);
     delete ctx;
 }
 

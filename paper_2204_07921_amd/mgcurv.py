@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_E_INVALID", -2: "MG_E
 class MgCurvParams(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
                 ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
-                ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32)]
+                ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32),
+                ("cycle", C.c_int32)]
 
 
 class MgFbsParams(C.Structure):
@@ -66,6 +67,9 @@ def _load() -> C.CDLL:
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.mg_curv_solve_target.restype = C.c_int
     L.mg_curv_solve_target.argtypes = [vp, vp, cvp, C.c_double, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.mg_curv_solve_rule.restype = C.c_int
+    L.mg_curv_solve_rule.argtypes = [vp, vp, cvp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double)]
     L.mg_curv_batch_solve_target.restype = C.c_int
     L.mg_curv_batch_solve_target.argtypes = [vp, vp, cvp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
                                              C.POINTER(C.c_double), C.POINTER(C.c_int32)]
@@ -248,6 +252,14 @@ def mg_curv_solve_target(ctx, params, u, f, target_energy: float, max_vcycles: i
     return {"status": st, "vcycles": done.value, "energy": fin.value}
 
 
+def mg_curv_solve_rule(ctx, params, u, f, stop: int, tol: float, max_vcycles: int = 1000):
+    done = C.c_int32()
+    fin = C.c_double()
+    st = _check(lib.mg_curv_solve_rule(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), int(stop),
+                                       float(tol), max_vcycles, C.byref(done), C.byref(fin)), ctx)
+    return {"status": st, "vcycles": done.value, "energy": fin.value}
+
+
 def mg_curv_energy(ctx, params, u, f) -> float:
     e = C.c_double()
     _check(lib.mg_curv_energy(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), C.byref(e)), ctx)
@@ -273,11 +285,11 @@ class Solver:
 
     def __init__(self, height: int, width: int, alpha: float = 20.0, kind: int = MG_CURV_MEAN,
                  levels: int = 0, dtype=torch.float32, fine_colours: int = 4, samples: int = 16,
-                 bisections: int = 32, stream=None):
+                 bisections: int = 32, stream=None, cycle: int = 0):
         self.params = default_params(height, width, alpha=float(alpha), curvature=int(kind), levels=int(levels),
                                      state_dtype=MG_F64 if dtype == torch.float64 else MG_F32,
                                      fine_colours=int(fine_colours), samples=int(samples),
-                                     bisections=int(bisections))
+                                     bisections=int(bisections), cycle=int(cycle))
         self.dtype = dtype
         self.ctx = mg_curv_init(self.params, stream)
         self.levels = lib.mg_curv_levels(self.ctx)
@@ -304,6 +316,9 @@ class Solver:
 
     def solve_target(self, u, f, target_energy, max_vcycles=1000):
         return mg_curv_solve_target(self.ctx, self.params, u, f, target_energy, max_vcycles)
+
+    def solve_rule(self, u, f, tol, max_vcycles=1000, stop=MG_STOP_RELERR_U):
+        return mg_curv_solve_rule(self.ctx, self.params, u, f, stop, tol, max_vcycles)
 
     def sweep(self, u, f, level, colour):
         return mg_curv_sweep(self.ctx, self.params, u, f, level, colour)

@@ -16,7 +16,8 @@ LIB = os.path.join(ROOT, "paper_2204_07921_amd", "libmgcurv.so")
 class Params(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
                 ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
-                ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32)]
+                ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32),
+                ("cycle", C.c_int32)]
 
 
 @pytest.fixture(scope="module")
@@ -54,15 +55,15 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_params_struct_layout(lib):
-    assert C.sizeof(Params) == 40
+    assert C.sizeof(Params) == 48
     p = Params()
     lib.mg_curv_default_params(C.byref(p), 64, 48)
     assert (p.height, p.width, p.alpha, p.curvature, p.levels, p.state_dtype) == (64, 48, 20.0, 0, 0, 0)
-    assert (p.fine_colours, p.samples, p.bisections) == (4, 16, 32)
+    assert (p.fine_colours, p.samples, p.bisections, p.cycle) == (4, 16, 32, 0)
 
 
 @pytest.mark.parametrize("field,value,status", [
-    ("height", 1, -2), ("width", 0, -2), ("alpha", 0.0, -1), ("alpha", float("nan"), -1),
+    ("height", 1, -2), ("width", 0, -2), ("alpha", 0.0, -1), ("alpha", float("nan"), -1), ("cycle", 2, -1),
     ("alpha", float("inf"), -1), ("curvature", 2, -1), ("state_dtype", 7, -3), ("fine_colours", 5, -1),
     ("samples", 3, -1), ("samples", 0, -1), ("bisections", -1, -1), ("bisections", 65, -1), ("levels", 99, -1),
 ])

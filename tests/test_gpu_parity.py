@@ -209,6 +209,62 @@ def test_solve_stop_rule_matches_oracle(mg, orc):
     assert np.max(np.abs(host(ug) - uo)) <= 1e-6
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_full_cycle_matches_level_composition_and_oracle(mg, orc, kind):
+    """Full V-cycle (levels 1..J then J-1..1, Section 2.2): the V-cycle call, in which coarse
+    levels hand their corrections to the next level's sums pass in both directions, equals the
+    same levels run one self-contained call at a time, bit for bit; and it matches the float-state
+    oracle's full cycle from the same start."""
+    h, w = 200, 170   # J = 8: levels 7 and 8 (b = 64, 128) are the lazily applied ones
+    _case(f"full cycle {h}x{w} kind={kind}")
+    f, _ = _f_and_u(h, w, 12, 0.1, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=torch.float32, cycle=1)
+    J = s.levels
+    fd = dev(f, torch.float32)
+    ua, ub = dev(f, torch.float32), dev(f, torch.float32)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=True, threads=THREADS, cycle=1)
+    uo = f.copy()
+    for rep in range(2):
+        s.vcycle(ua, fd)
+        for level in list(range(1, J + 1)) + list(range(J - 1, 0, -1)):
+            s.level(ub, fd, level)
+        assert torch.equal(ua, ub), rep
+        o.vcycle(uo, f)
+        du = np.max(np.abs(host(ua) - uo))
+        print(f"full cycle {rep + 1}: max |du| vs oracle {du:.3e}")
+        assert du <= 1e-6
+    half = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=torch.float32)
+    uh = dev(f, torch.float32)
+    half.vcycle(uh, fd)
+    assert not torch.equal(uh, ua)
+
+
+@pytest.mark.parametrize("cycle", [0, 1])
+def test_relerr_stop_rule_matches_oracle(mg, orc, cycle):
+    """relErr(u) stop (Section 4): same number of V-cycles, final energy and state as the oracle."""
+    h, w = 80, 72
+    _case(f"relErr stop cycle={cycle}")
+    # float state against the oracle's float-state option, as for the energy rule: both sides
+    # round the same FP64 corrections to float, so states and norms agree
+    f, _ = _f_and_u(h, w, 9, 0.08, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=0, dtype=torch.float32, cycle=cycle)
+    ug = dev(f, torch.float32)
+    res = s.solve_rule(ug, dev(f, torch.float32), 1e-3, max_vcycles=200, stop=mg.MG_STOP_RELERR_U)
+    o = orc.Oracle(h, w, 20.0, 0, round_f32=True, threads=THREADS, cycle=cycle)
+    uo = f.copy()
+    n, trace = o.solve_rule(uo, f, 1e-3, max_vcycles=200, stop=1)
+    print(f"gpu vcycles={res['vcycles']} oracle={n}")
+    assert res["status"] == 0
+    assert res["vcycles"] == n
+    assert abs(res["energy"] - trace[-1]) <= 1e-9 * trace[-1]
+    assert np.max(np.abs(host(ug) - uo)) <= 1e-6
+    # the energy rule through the same entry point is mg_curv_solve
+    ue = dev(f, torch.float32)
+    r2 = s.solve_rule(ue, dev(f, torch.float32), 1e-6, max_vcycles=300, stop=mg.MG_STOP_ENERGY)
+    r3 = s.solve(dev(f, torch.float32), dev(f, torch.float32), rel_tol=1e-6, max_vcycles=300)
+    assert r2["vcycles"] == r3["vcycles"] and r2["energy"] == r3["energy"]
+
+
 def test_not_converged_status(mg):
     f, _ = _f_and_u(32, 32, 1, 0.1, torch.float32)
     s = mg.Solver(32, 32, dtype=torch.float32)
