@@ -4,18 +4,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mgc_device.h"
+
 namespace fbs {
 
 constexpr double SQRT2 = 1.4142135623730951;
 
-// 1/sqrt(x) for finite x >= 1 (here x >= l^2 >= 1): the hardware estimate (relative error
-// about 2^-24) and one step of the series y (1 + e/2 + 3e^2/8), e = 1 - x y^2.
-__device__ __forceinline__ double rsqrt_pos(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
+using mgc::rsqrt_pos;   // refined hardware 1/sqrt; the arguments here are >= l^2 >= 1
 
 // The value of lane (l xor OFF): a DPP quad permutation for OFF = 1 and 2 (no LDS
 // round trip), the LDS permute otherwise.

@@ -465,17 +465,16 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     if (n == 0) return MG_OK;
     const int G = lanes_for(bs);
     const int ng = groups_grid(n, G);        // workgroups of the patch-wise kernels
-    const int ngc = ng;                      // (the iteration's kernels stride, any grid is correct)
     const int nv = (n + 255) / 256;          // workgroups of the vector kernels
     const dim3 blk(256), gp = rec::pixel_grid(H, W);
     const int diagonal = bs >= 5;
     hipLaunchKernelGGL(rec::residual_kernel<T>, gp, blk, 0, st, (const T*)u, (const T*)b, H, W, c->blur, c->t);
 #define REC_G(KERNEL, ...)                                                                        \
     switch (G) {                                                                                  \
-    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;          \
-    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;          \
-    case 64: hipLaunchKernelGGL((KERNEL<64>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;        \
-    default: hipLaunchKernelGGL((KERNEL<256>), dim3(ngc), blk, 0, st, __VA_ARGS__); break;       \
+    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(ng), blk, 0, st, __VA_ARGS__); break;          \
+    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(ng), blk, 0, st, __VA_ARGS__); break;          \
+    case 64: hipLaunchKernelGGL((KERNEL<64>), dim3(ng), blk, 0, st, __VA_ARGS__); break;        \
+    default: hipLaunchKernelGGL((KERNEL<256>), dim3(ng), blk, 0, st, __VA_ARGS__); break;       \
     }
     switch (G) {
     case 1: hipLaunchKernelGGL((rec::rhs_kernel<T, 1>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
@@ -493,7 +492,7 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
         else
             hipLaunchKernelGGL(rec::blur_expand_kernel<0>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
         REC_G(rec::gram_kernel, (const double*)c->w, H, W, c->blur, cg, c->P.alpha, (const double*)c->pv, c->qv, c->part_a);
-        hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, ngc,
+        hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, ng,
                            (const double*)c->scal, k_old, c->x, c->r, (const double*)c->pv, (const double*)c->qv, c->part_b);
         hipLaunchKernelGGL(rec::update_p_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_b, nv, c->scal, k_old,
                            k_new, (const double*)c->r, c->pv);
