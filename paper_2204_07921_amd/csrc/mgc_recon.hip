@@ -113,53 +113,29 @@ __global__ __launch_bounds__(256) void residual_kernel(const T* __restrict__ u, 
     }
 }
 
-// w = A v with v = sum over colour-k patches of pv_i phi_i (zero elsewhere and outside)
-// BS > 0: the patch side as a compile-time constant (the divisions by it become multiplications).
-template <int BS>
-__global__ __launch_bounds__(256) void blur_expand_kernel(const double* __restrict__ pv, int H, int W, ColourGrid cg,
-                                                          Blur bl, double* __restrict__ w)
+// One factor of <A phi_i, A phi_l> (the Gaussian is separable, so the inner product of two
+// blurred patch indicators is a product of a row and a column factor): the overlap, over the n
+// rows of the image, of the blurred indicators of rows [a1, e1) and [a2, e2).
+__host__ __device__ inline double blur_overlap(const Blur& bl, int a1, int e1, int a2, int e2, int n)
 {
-    const int b = BS > 0 ? BS : cg.b;
-    REC_PIXELS {
-        // patch row / column of the five rows and columns around (i, j), and whether they have colour k
-        int prow[5], pcol[5];
-        bool rok[5], cok[5];
-#pragma unroll
-        for (int d = 0; d < 5; ++d) {
-            const int ii = i + d - RB, jj = j + d - RB;
-            rok[d] = ii >= 0 && ii < H;
-            cok[d] = jj >= 0 && jj < W;
-            prow[d] = rok[d] ? ii / b : 0;
-            pcol[d] = cok[d] ? jj / b : 0;
-            rok[d] = rok[d] && (prow[d] & 1) == cg.pr;
-            cok[d] = cok[d] && (pcol[d] & 1) == cg.pc;
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int dy = 0; dy < 5; ++dy) {
-            if (!rok[dy]) continue;
-            const double* row = pv + (size_t)prow[dy] * cg.nj;
-#pragma unroll
-            for (int dx = 0; dx < 5; ++dx)
-                if (cok[dx]) acc += bl.w[dy * 5 + dx] * row[pcol[dx]];
-        }
-        w[(size_t)i * W + j] = acc;
-    }
-}
-
-// Squared norm of the blurred indicator of rows [a, e) of an image of n rows,
-// one factor of <A phi, A phi> (the Gaussian is separable).
-__device__ __forceinline__ double blur_factor(const Blur& bl, int a, int e, int n)
-{
+    const int lo = max(0, max(a1, a2) - RB), hi = min(n, min(e1, e2) + RB);   // both nonzero only here
     double s = 0.0;
-    for (int i = max(0, a - RB); i < min(n, e + RB); ++i) {
-        double r = 0.0;
+    for (int i = lo; i < hi; ++i) {
+        double r1 = 0.0, r2 = 0.0;
 #pragma unroll
-        for (int d = -RB; d <= RB; ++d)
-            if (i + d >= a && i + d < e) r += bl.g[d + RB];
-        s += r * r;
+        for (int d = -RB; d <= RB; ++d) {
+            if (i + d >= a1 && i + d < e1) r1 += bl.g[d + RB];
+            if (i + d >= a2 && i + d < e2) r2 += bl.g[d + RB];
+        }
+        s += r1 * r2;
     }
     return s;
+}
+
+// Squared norm of the blurred indicator of rows [a, e): the diagonal factor.
+__host__ __device__ inline double blur_factor(const Blur& bl, int a, int e, int n)
+{
+    return blur_overlap(bl, a, e, a, e, n);
 }
 
 // Patch (p, q) of a colour-grid index.
@@ -267,29 +243,55 @@ __global__ __launch_bounds__(256) void scalar_kernel(const double* __restrict__ 
     if (threadIdx.x == 0) scal[k] = s;
 }
 
-// q_i = sum_patch A^T w + 2 alpha p_i; partials of p . q
-template <int G>
-__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ w, int H, int W, Blur bl, ColourGrid cg,
-                                                   double alpha, const double* __restrict__ pv, double* __restrict__ qv,
-                                                   double* __restrict__ part_pq)
+// Row (or column) factors of one colour's Gram matrix G_il = <A phi_i, A phi_l>:
+// tab[k * (2 DH + 1) + d + DH] = blur_overlap of the colour's patch row k and patch row k + d
+// (rows p = 2k + par of the level's m patch rows of side b in an image of n rows; 0 where row
+// k + d does not exist).  Two patches of one colour interact only if their blurred indicators
+// (each reaching RB pixels beyond the patch) overlap: |2d| b < b + 2 RB.
+__global__ __launch_bounds__(256) void overlap_table_kernel(Blur bl, int b, int n, int m, int par, int cnt, int DH,
+                                                            double* __restrict__ tab)
+{
+    const int ND = 2 * DH + 1;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt * ND; t += gridDim.x * blockDim.x) {
+        const int k = t / ND, d = t - k * ND - DH;
+        const int p = 2 * k + par, p2 = p + 2 * d;
+        double v = 0.0;
+        if (p2 >= 0 && p2 < m) v = blur_overlap(bl, p * b, min(p * b + b, n), p2 * b, min(p2 * b + b, n), n);
+        tab[t] = v;
+    }
+}
+
+// q = (G + 2 alpha I) p on one colour, G_il = row factor x column factor, and partials of p . q.
+template <int DH>
+__global__ __launch_bounds__(256) void gram_stencil_kernel(const double* __restrict__ pv, ColourGrid cg,
+                                                           const double* __restrict__ tab_r,
+                                                           const double* __restrict__ tab_c, double alpha,
+                                                           double* __restrict__ qv, double* __restrict__ part_pq)
 {
     __shared__ double lds[4];
-    constexpr int PER = 256 / G;   // lane groups per workgroup; the grid strides over the patches
-    const int lane = threadIdx.x % G, n = cg.count(), b = cg.b;
+    constexpr int ND = 2 * DH + 1;
     double pq = 0.0;
-    for (int g0 = blockIdx.x * PER; g0 < n; g0 += gridDim.x * PER) {
-        const int gid = g0 + threadIdx.x / G;
-        if (gid >= n) continue;   // whole lane groups
-        int p, q;
-        patch_of(cg, gid, p, q);
-        const int r0 = p * b, r1 = min(r0 + b, H), c0 = q * b, c1 = min(c0 + b, W);
-        const double s = patch_adjoint_sum<G>(w, H, W, bl, r0, r1, c0, c1, lane);
-        if (lane == 0) {
-            const size_t id = (size_t)p * cg.nj + q;
-            const double qi = s + 2.0 * alpha * pv[id];
-            qv[id] = qi;
-            pq += pv[id] * qi;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cg.count(); g += gridDim.x * blockDim.x) {
+        const int a = g / cg.nb, c = g - a * cg.nb;
+        double acc = 0.0;
+#pragma unroll
+        for (int da = -DH; da <= DH; ++da) {
+            const int a2 = a + da;
+            if (a2 < 0 || a2 >= cg.na) continue;
+            const double* prow = pv + (size_t)(2 * a2 + cg.pr) * cg.nj + cg.pc;
+            double row = 0.0;
+#pragma unroll
+            for (int dc = -DH; dc <= DH; ++dc) {
+                const int c2 = c + dc;
+                if (c2 < 0 || c2 >= cg.nb) continue;
+                row += tab_c[c * ND + dc + DH] * prow[2 * c2];
+            }
+            acc += tab_r[a * ND + da + DH] * row;
         }
+        const size_t id = (size_t)(2 * a + cg.pr) * cg.nj + 2 * c + cg.pc;
+        const double qi = fma(2.0 * alpha, pv[id], acc);
+        qv[id] = qi;
+        pq += pv[id] * qi;
     }
     const double tot = block_total<256>(pq, lds);
     if (threadIdx.x == 0) part_pq[blockIdx.x] = tot;
@@ -398,7 +400,7 @@ struct mg_recon_ctx {
     hipStream_t gstream;     // own stream, only for capturing graphs (default priority)
     rec::Blur blur;
     double* t;               // H x W FP64: b - A u
-    double* w;               // H x W FP64: A v
+    double* tab;             // Gram row and column factors of one colour: 5 (H + W) doubles
     double* x;               // patch arrays (largest level grid)
     double* r;
     double* pv;
@@ -469,13 +471,6 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     const dim3 blk(256), gp = rec::pixel_grid(H, W);
     const int diagonal = bs >= 5;
     hipLaunchKernelGGL(rec::residual_kernel<T>, gp, blk, 0, st, (const T*)u, (const T*)b, H, W, c->blur, c->t);
-#define REC_G(KERNEL, ...)                                                                        \
-    switch (G) {                                                                                  \
-    case 1: hipLaunchKernelGGL((KERNEL<1>), dim3(ng), blk, 0, st, __VA_ARGS__); break;          \
-    case 8: hipLaunchKernelGGL((KERNEL<8>), dim3(ng), blk, 0, st, __VA_ARGS__); break;          \
-    case 64: hipLaunchKernelGGL((KERNEL<64>), dim3(ng), blk, 0, st, __VA_ARGS__); break;        \
-    default: hipLaunchKernelGGL((KERNEL<256>), dim3(ng), blk, 0, st, __VA_ARGS__); break;       \
-    }
     switch (G) {
     case 1: hipLaunchKernelGGL((rec::rhs_kernel<T, 1>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
     case 8: hipLaunchKernelGGL((rec::rhs_kernel<T, 8>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
@@ -483,21 +478,30 @@ mg_status colour_sweep(mg_recon_ctx* c, hipStream_t st, void* u, const void* b, 
     default: hipLaunchKernelGGL((rec::rhs_kernel<T, 256>), dim3(ng), blk, 0, st, (const T*)u, (const double*)c->t, H, W, c->blur, cg, c->P.alpha, diagonal, c->x, c->r, c->pv, c->part_b); break;
     }
     if (!diagonal) hipLaunchKernelGGL(rec::scalar_kernel, dim3(1), blk, 0, st, (const double*)c->part_b, ng, c->scal, 0);
+    // the colour's Gram factors (the operator depends only on the geometry and A)
+    const int dh = (2 * rec::RB + bs) / (2 * bs);   // largest |d| with |2d| b < b + 2 RB
+    double* tab_r = c->tab;
+    double* tab_c = c->tab + (size_t)cg.na * (2 * dh + 1);
+    if (!diagonal) {
+        const int nr = cg.na * (2 * dh + 1), nc = cg.nb * (2 * dh + 1);
+        hipLaunchKernelGGL(rec::overlap_table_kernel, dim3((nr + 255) / 256), blk, 0, st, c->blur, bs, H, cg.mj, cg.pr,
+                           cg.na, dh, tab_r);
+        hipLaunchKernelGGL(rec::overlap_table_kernel, dim3((nc + 255) / 256), blk, 0, st, c->blur, bs, W, cg.nj, cg.pc,
+                           cg.nb, dh, tab_c);
+    }
     for (int it = 0; it < (diagonal ? 0 : c->P.cg_iters); ++it) {
         const int k_old = it & 1, k_new = k_old ^ 1;
-        if (bs == 1)
-            hipLaunchKernelGGL(rec::blur_expand_kernel<1>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
-        else if (bs == 3)
-            hipLaunchKernelGGL(rec::blur_expand_kernel<3>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
+        if (dh == 2)
+            hipLaunchKernelGGL(rec::gram_stencil_kernel<2>, dim3(nv), blk, 0, st, (const double*)c->pv, cg,
+                               (const double*)tab_r, (const double*)tab_c, c->P.alpha, c->qv, c->part_a);
         else
-            hipLaunchKernelGGL(rec::blur_expand_kernel<0>, gp, blk, 0, st, (const double*)c->pv, H, W, cg, c->blur, c->w);
-        REC_G(rec::gram_kernel, (const double*)c->w, H, W, c->blur, cg, c->P.alpha, (const double*)c->pv, c->qv, c->part_a);
-        hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, ng,
+            hipLaunchKernelGGL(rec::gram_stencil_kernel<1>, dim3(nv), blk, 0, st, (const double*)c->pv, cg,
+                               (const double*)tab_r, (const double*)tab_c, c->P.alpha, c->qv, c->part_a);
+        hipLaunchKernelGGL(rec::update_xr_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_a, nv,
                            (const double*)c->scal, k_old, c->x, c->r, (const double*)c->pv, (const double*)c->qv, c->part_b);
         hipLaunchKernelGGL(rec::update_p_kernel, dim3(nv), blk, 0, st, cg, (const double*)c->part_b, nv, c->scal, k_old,
                            k_new, (const double*)c->r, c->pv);
     }
-#undef REC_G
     hipLaunchKernelGGL(rec::apply_kernel<T>, gp, blk, 0, st, (T*)u, H, W, cg, (const double*)c->x);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MG_OK : rhip(c, e, "reconstruction sweep launch");
@@ -641,7 +645,7 @@ mg_status mg_recon_init(const mg_recon_params* params, void* hip_stream, mg_reco
     c->P = p;
     c->stream = (hipStream_t)hip_stream;
     c->gstream = nullptr;
-    c->t = c->w = c->x = c->r = c->pv = c->qv = c->part_a = c->part_b = c->scal = c->host1 = nullptr;
+    c->t = c->tab = c->x = c->r = c->pv = c->qv = c->part_a = c->part_b = c->scal = c->host1 = nullptr;
     c->norms_part = nullptr;
     c->prev = nullptr;
     c->graph = nullptr;
@@ -676,7 +680,8 @@ mg_status mg_recon_init(const mg_recon_params* params, void* hip_stream, mg_reco
     const size_t img = (size_t)p.height * p.width;
     const size_t npart = (size_t)(maxgroups > rec::GRID_PIX ? maxgroups : rec::GRID_PIX);
     if (hipMalloc((void**)&c->t, img * 8) != hipSuccess ||
-        hipMalloc((void**)&c->w, img * 8) != hipSuccess || hipMalloc((void**)&c->x, npatch * 8) != hipSuccess ||
+        hipMalloc((void**)&c->tab, (size_t)5 * (p.height + p.width) * 8) != hipSuccess ||
+        hipMalloc((void**)&c->x, npatch * 8) != hipSuccess ||
         hipMalloc((void**)&c->r, npatch * 8) != hipSuccess || hipMalloc((void**)&c->pv, npatch * 8) != hipSuccess ||
         hipMalloc((void**)&c->qv, npatch * 8) != hipSuccess || hipMalloc((void**)&c->part_a, npart * 8) != hipSuccess ||
         hipMalloc((void**)&c->part_b, npart * 8) != hipSuccess || hipMalloc((void**)&c->scal, 8 * 8) != hipSuccess ||
@@ -767,7 +772,7 @@ void mg_recon_destroy(mg_recon_ctx* ctx)
     if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
     drop_graph(ctx);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
-    for (double* q : {ctx->t, ctx->w, ctx->x, ctx->r, ctx->pv, ctx->qv, ctx->part_a, ctx->part_b, ctx->scal,
+    for (double* q : {ctx->t, ctx->tab, ctx->x, ctx->r, ctx->pv, ctx->qv, ctx->part_a, ctx->part_b, ctx->scal,
                       ctx->norms_part})
         if (q) (void)hipFree(q);
     if (ctx->prev) (void)hipFree(ctx->prev);
