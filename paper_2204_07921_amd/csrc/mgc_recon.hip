@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void rhs_kernel(const T* __restrict__ u, const
         for (int off = 1; off < G; off <<= 1) sum += __shfl_xor(sum, off, 64);
         const double d = sum / (double)(8 * R);
         const double ri = patch_adjoint_sum<G>(t, H, W, bl, r0, r1, c0, c1, lane) + 2.0 * alpha * d;
-        const size_t id = (size_t)p * cg.nj + q;
+        const size_t id = (size_t)gid;   // patch vectors are stored in colour-grid order
         if (lane == 0) {
             if (diagonal) {
                 const double gii = blur_factor(bl, r0, r1, H) * blur_factor(bl, c0, c1, W);
@@ -278,17 +278,17 @@ __global__ __launch_bounds__(256) void gram_stencil_kernel(const double* __restr
         for (int da = -DH; da <= DH; ++da) {
             const int a2 = a + da;
             if (a2 < 0 || a2 >= cg.na) continue;
-            const double* prow = pv + (size_t)(2 * a2 + cg.pr) * cg.nj + cg.pc;
+            const double* prow = pv + (size_t)a2 * cg.nb;
             double row = 0.0;
 #pragma unroll
             for (int dc = -DH; dc <= DH; ++dc) {
                 const int c2 = c + dc;
                 if (c2 < 0 || c2 >= cg.nb) continue;
-                row += tab_c[c * ND + dc + DH] * prow[2 * c2];
+                row += tab_c[c * ND + dc + DH] * prow[c2];
             }
             acc += tab_r[a * ND + da + DH] * row;
         }
-        const size_t id = (size_t)(2 * a + cg.pr) * cg.nj + 2 * c + cg.pc;
+        const size_t id = (size_t)g;
         const double qi = fma(2.0 * alpha, pv[id], acc);
         qv[id] = qi;
         pq += pv[id] * qi;
@@ -310,9 +310,7 @@ __global__ __launch_bounds__(256) void update_xr_kernel(ColourGrid cg, const dou
     const double a = pq > 0.0 ? rr / pq : 0.0;
     double acc = 0.0;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cg.count(); g += gridDim.x * blockDim.x) {
-        int p, q;
-        patch_of(cg, g, p, q);
-        const size_t id = (size_t)p * cg.nj + q;
+        const size_t id = (size_t)g;
         x[id] += a * pv[id];
         const double rn = r[id] - a * qv[id];
         r[id] = rn;
@@ -332,9 +330,7 @@ __global__ __launch_bounds__(256) void update_p_kernel(ColourGrid cg, const doub
     const double ro = scal[k_old];
     const double beta = ro > 0.0 ? rn / ro : 0.0;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cg.count(); g += gridDim.x * blockDim.x) {
-        int p, q;
-        patch_of(cg, g, p, q);
-        const size_t id = (size_t)p * cg.nj + q;
+        const size_t id = (size_t)g;
         pv[id] = r[id] + beta * pv[id];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[k_new] = rn;
@@ -348,7 +344,7 @@ __global__ __launch_bounds__(256) void apply_kernel(T* __restrict__ u, int H, in
     REC_PIXELS {
         const int p = i / cg.b, q = j / cg.b;
         if ((p & 1) == cg.pr && (q & 1) == cg.pc) {
-            const double c = x[(size_t)p * cg.nj + q];
+            const double c = x[(size_t)(p >> 1) * cg.nb + (q >> 1)];   // colour-grid order
             const size_t k = (size_t)i * W + j;
             if (c != 0.0) u[k] = (T)((double)u[k] + c);
         }
@@ -401,7 +397,7 @@ struct mg_recon_ctx {
     rec::Blur blur;
     double* t;               // H x W FP64: b - A u
     double* tab;             // Gram row and column factors of one colour: 5 (H + W) doubles
-    double* x;               // patch arrays (largest level grid)
+    double* x;               // patch vectors of one colour, in colour-grid order (a * nb + c)
     double* r;
     double* pv;
     double* qv;
