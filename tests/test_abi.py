@@ -85,6 +85,11 @@ def test_null_arguments(lib):
     assert lib.mg_curv_energy(None, None, None, None) == -1
     assert lib.mg_curv_sweep(None, None, None, 1, 0) == -1
     assert lib.mg_curv_level(None, None, None, 1) == -1
+    lib.mg_curv_solve_rule.restype = C.c_int
+    lib.mg_curv_solve_rule.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int32,
+                                       C.c_void_p, C.c_void_p]
+    for stop in (0, 1, 7):
+        assert lib.mg_curv_solve_rule(None, None, None, stop, 1e-4, 10, None, None) == -1
     lib.mg_curv_destroy(None)
 
 

@@ -384,3 +384,11 @@ def test_error_paths(mg):
         s.vcycle(dev(f[:16], torch.float32), fd)
     with pytest.raises(TypeError):
         s.vcycle(dev(f, torch.float64), fd)
+    with pytest.raises(mg.MgCurvError) as ei:
+        s.solve_rule(dev(f, torch.float32), fd, 1e-4, max_vcycles=3, stop=7)
+    assert ei.value.status == -1
+    r = s.solve_rule(dev(f, torch.float32), fd, 0.0, max_vcycles=3, stop=mg.MG_STOP_RELERR_U)
+    assert r["status"] == 0 and r["vcycles"] == 3
+    with pytest.raises(mg.MgCurvError) as ei:
+        mg.Solver(32, 32, dtype=torch.float32, cycle=2)
+    assert ei.value.status == -1
