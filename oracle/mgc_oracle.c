@@ -17,8 +17,10 @@
  *    boundary conditions, Section 2.2; reading R3);
  *  - the discrete energy F(u) = sum |kappa(u)| + alpha/2 (u - f)^2 of
  *    eq. (MCM) and eq. (GCM);
- *  - the block hierarchy of Section 2.2 with block side b_j = 2^(j-1)
- *    (reading R4), blocks clipped at the right and bottom edges;
+ *  - the block hierarchy of Section 2.2, blocks clipped at the right and
+ *    bottom edges, with block side b_j = 2^(j-1) (schedule 0, reading R4:
+ *    nested blocks) or the paper's b_j = 2^j - 1 (schedule 1, Section 2.2's
+ *    patch side, m_j = ceil(m / (2^j - 1)) blocks along a side of m pixels);
  *  - the four-colour decomposition of Section 2.3 (colour of block (p, q) is
  *    2 (p mod 2) + (q mod 2), colours visited in the order 0, 1, 2, 3);
  *  - Algorithm 3: fine-to-coarse half V-cycle (or, with cycle = 1, the full
@@ -57,13 +59,14 @@ typedef struct {
     int32_t height, width;
     double alpha;
     int32_t kind;          /* 0 mean curvature, 1 Gaussian curvature */
-    int32_t levels;        /* J; block side at level j (1-based) is 2^(j-1) */
+    int32_t levels;        /* J; block side at level j (1-based): see orc_block_side */
     int32_t fine_colours;  /* 4 (paper) or 9 (exactly non-interacting at b = 1) */
     int32_t samples;       /* M, even */
     int32_t bisections;    /* G */
     int32_t round_f32;     /* 1: round the state to float after each update */
     int32_t threads;       /* OpenMP threads for the per-colour block loop */
     int32_t cycle;         /* 0: levels 1..J (the half V-cycle of Algorithm 3); 1: then J-1..1 */
+    int32_t schedule;      /* block side at level j: 0 -> 2^(j-1), 1 -> 2^j - 1 (Section 2.2) */
 } orc_params;
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -337,7 +340,12 @@ double orc_local_solve(const orc_params *P, const double *u, const double *f,
 /* ------------------------------------------------------------------------ */
 /* Level geometry and colour sweeps (Section 2.2-2.3, Algorithm 3).          */
 /* ------------------------------------------------------------------------ */
-int orc_block_side(int level) { return 1 << (level - 1); }
+/* Block side at level j (1-based): 2^(j-1) (schedule 0) or 2^j - 1 (schedule 1,
+ * the patch side of Section 2.2).  Both give single pixels at j = 1. */
+int orc_block_side(const orc_params *P, int level)
+{
+    return P->schedule == 1 ? (1 << level) - 1 : 1 << (level - 1);
+}
 
 int orc_num_colours(const orc_params *P, int level)
 {
@@ -355,7 +363,7 @@ static int colour_of(int ncol, int p, int q)
  * blocks of that colour. */
 int orc_sweep(const orc_params *P, double *u, const double *f, int level, int colour, double *cbuf)
 {
-    const int H = P->height, W = P->width, b = orc_block_side(level);
+    const int H = P->height, W = P->width, b = orc_block_side(P, level);
     const int mj = (H + b - 1) / b, nj = (W + b - 1) / b;
     const int ncol = orc_num_colours(P, level);
     int nblk = 0;

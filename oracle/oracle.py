@@ -38,7 +38,7 @@ class OracleParams(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
                 ("kind", C.c_int32), ("levels", C.c_int32), ("fine_colours", C.c_int32),
                 ("samples", C.c_int32), ("bisections", C.c_int32), ("round_f32", C.c_int32),
-                ("threads", C.c_int32), ("cycle", C.c_int32)]
+                ("threads", C.c_int32), ("cycle", C.c_int32), ("schedule", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -93,6 +93,8 @@ def _load():
         L.orc_solve_rule.argtypes = [P, _DP, _DP, C.c_double, C.c_int, C.c_int, C.c_void_p]
         L.orc_num_colours.restype = C.c_int
         L.orc_num_colours.argtypes = [P, C.c_int]
+        L.orc_block_side.restype = C.c_int
+        L.orc_block_side.argtypes = [P, C.c_int]
         FP = C.POINTER(FbsParams)
         L.fbs_plane.restype = None
         L.fbs_plane.argtypes = [FP, _DP, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
@@ -141,11 +143,11 @@ class Oracle:
 
     def __init__(self, height: int, width: int, alpha: float, kind: int = 0, levels: int = 0,
                  fine_colours: int = 4, samples: int = 16, bisections: int = 32,
-                 round_f32: bool = False, threads: int = 1, cycle: int = 0):
+                 round_f32: bool = False, threads: int = 1, cycle: int = 0, schedule: int = 0):
         if levels <= 0:
             levels = default_levels(height, width)
         self.p = OracleParams(height, width, float(alpha), kind, levels, fine_colours,
-                              samples, bisections, int(bool(round_f32)), threads, int(cycle))
+                              samples, bisections, int(bool(round_f32)), threads, int(cycle), int(schedule))
         self.L = _load()
 
     # geometry -------------------------------------------------------------
@@ -154,7 +156,7 @@ class Oracle:
         return self.p.levels
 
     def block_side(self, level: int) -> int:
-        return 1 << (level - 1)
+        return self.L.orc_block_side(C.byref(self.p), level)
 
     def grid(self, level: int) -> tuple[int, int]:
         b = self.block_side(level)

@@ -41,6 +41,10 @@ MUTANTS = [
     ("no_accept_test", "int accepted = delta < eta;", "int accepted = 1;"),
     ("colour_map", "return ncol == 9 ? 3 * (p % 3) + (q % 3) : 2 * (p % 2) + (q % 2);",
      "return ncol == 9 ? 3 * (p % 3) + (q % 3) : 2 * (q % 2) + (p % 2);"),
+    ("schedule_side_pow2", "return P->schedule == 1 ? (1 << level) - 1 : 1 << (level - 1);",
+     "return P->schedule == 1 ? (1 << level) : 1 << (level - 1);"),
+    ("schedule_level_shift", "return P->schedule == 1 ? (1 << level) - 1 : 1 << (level - 1);",
+     "return P->schedule == 1 ? (1 << (level + 1)) - 1 : 1 << (level - 1);"),
 ]
 
 

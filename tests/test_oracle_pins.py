@@ -381,3 +381,82 @@ def test_relerr_stop_rule_is_the_first_small_step(orc):
     o = orc.Oracle(H, W, 20.0, 1)
     n, _ = o.solve_rule(c.copy(), c, 1e-9, max_vcycles=10, stop=1)
     assert n == 1
+
+
+def test_paper_block_schedule_geometry(orc):
+    """Section 2.2's hierarchy: patch side 2^j - 1 and m_j = ceil(m / (2^j - 1)) patches along a
+    side of m pixels.  The expected values are worked by hand for a 100 x 37 image; the nested
+    power-of-two schedule is the default, and at j = 1 both are single pixels."""
+    o = orc.Oracle(100, 37, 20.0, 0, levels=6, schedule=1)
+    assert [o.block_side(j) for j in range(1, 7)] == [1, 3, 7, 15, 31, 63]
+    assert [o.grid(j) for j in range(1, 7)] == [(100, 37), (34, 13), (15, 6), (7, 3), (4, 2), (2, 1)]
+    o0 = orc.Oracle(100, 37, 20.0, 0, levels=6)
+    assert [o0.block_side(j) for j in range(1, 7)] == [1, 2, 4, 8, 16, 32]
+    assert [o0.grid(j) for j in range(1, 7)] == [(100, 37), (50, 19), (25, 10), (13, 5), (7, 3), (4, 2)]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_paper_schedule_sweeps_move_whole_patches(orc, kind):
+    """With the 2^j - 1 schedule a colour sweep at level j adds one constant to every patch of side
+    2^j - 1 (clipped at the right and bottom) whose colour 2 (P mod 2) + (Q mod 2) is the sweep's,
+    and leaves every other pixel bitwise alone; each constant is the local solver's on that patch,
+    from the state before the sweep.  The patch side is written here, not taken from the oracle."""
+    H, W = 23, 19
+    f, _ = noisy_image(H, W, 21, 0.1)
+    o = orc.Oracle(H, W, 20.0, kind, levels=3, schedule=1)
+    u = f.copy()
+    o.vcycle(u, f)
+    moved = 0
+    for j in (2, 3):
+        b = 2 ** j - 1
+        for colour in range(4):
+            before = u.copy()
+            expect = u.copy()
+            for P in range(-(-H // b)):
+                for Q in range(-(-W // b)):
+                    if 2 * (P % 2) + (Q % 2) != colour:
+                        continue
+                    bnd = (P * b, min(P * b + b, H), Q * b, min(Q * b + b, W))
+                    c = o.local_solve(before, f, bnd).c
+                    expect[bnd[0]:bnd[1], bnd[2]:bnd[3]] += c
+                    moved += c != 0.0
+            o.sweep(u, f, j, colour)
+            assert np.array_equal(u, expect), (j, colour)
+    assert moved > 20
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_paper_schedule_sweeps_monotone_and_separable(orc, kind):
+    """P5 + P9 on the 2^j - 1 patches: with nine fine colours every colour sweep changes F by the
+    sum of its patches' local changes, none positive (same-colour patches are at least one patch
+    apart, so their rings do not meet); a full solve never raises F."""
+    H, W = 26, 22
+    f, _ = noisy_image(H, W, 12, 0.08)
+    o = orc.Oracle(H, W, 20.0, kind, fine_colours=9, levels=4, schedule=1)
+    u = f.copy()
+    for level in range(1, o.levels + 1):
+        for colour in range(o.num_colours(level)):
+            E0 = o.energy(u, f)
+            deltas = []
+            for p, q, bnd in _blocks(o, level):
+                if o.colour_of(level, p, q) != colour:
+                    continue
+                info = o.local_solve(u, f, bnd)
+                deltas.append(info.delta if info.accepted else 0.0)
+            o.sweep(u, f, level, colour)
+            E1 = o.energy(u, f)
+            assert abs((E1 - E0) - sum(deltas)) < 1e-10 * (1 + E0), (level, colour)
+            assert E1 <= E0 + 1e-10 * (1 + E0)
+    v = f.copy()
+    _, trace = o.solve(v, f, rel_tol=0.0, max_vcycles=4)
+    assert np.all(np.diff(trace) <= 1e-10 * trace[0])
+
+
+def test_paper_schedule_single_level_equals_pixel_level(orc):
+    """At J = 1 both schedules are the pixel level: one V-cycle agrees bitwise."""
+    f, _ = noisy_image(19, 24, 3, 0.1)
+    a, b = f.copy(), f.copy()
+    orc.Oracle(19, 24, 20.0, 0, levels=1).vcycle(a, f)
+    orc.Oracle(19, 24, 20.0, 0, levels=1, schedule=1).vcycle(b, f)
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, f)
