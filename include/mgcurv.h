@@ -79,20 +79,24 @@ typedef struct {
     int32_t cycle;         /* 0: levels 1..J, the half V-cycle of Algorithm 3 (default);
                               1: then J-1..1, the full V-cycle Section 2.2 compares it with.
                               Batches take 0 only. */
+    int32_t block_schedule; /* block side at level j: 0: 2^(j-1), nested blocks (default);
+                              1: 2^j - 1, the patch side of Section 2.2 (blocks of one
+                              level then straddle those of the next).  Both are single
+                              pixels at j = 1.  Batches take 0 only. */
 } mg_curv_params;
 
 typedef struct mg_curv_ctx mg_curv_ctx;
 
 /* Fill *p with the defaults for an H x W image: alpha 20, mean curvature,
  * levels 0 (automatic), float state, 4 fine colours, M = 16, G = 32, half
- * V-cycle. */
+ * V-cycle, power-of-two blocks. */
 void mg_curv_default_params(mg_curv_params *p, int32_t height, int32_t width);
 
 /* Validate *params, bind the current HIP device and `hip_stream`
  * (a hipStream_t, may be NULL), and allocate the context's scratch: one
  * H x W ping-pong image for the pixel level, the energy partial sums, the
  * coarse levels' block sums and two arrays of pending corrections, and, when
- * the levels reach blocks of side >= 1024, the expanded ring records of one
+ * the levels reach blocks of side >= 1023, the expanded ring records of one
  * colour's blocks (7 doubles per ring pixel; 7.3 MB at 8192 x 8192).
  * On success *out receives a context the caller releases with
  * mg_curv_destroy.  Errors: MG_E_INVALID / MG_E_SHAPE / MG_E_DTYPE for bad

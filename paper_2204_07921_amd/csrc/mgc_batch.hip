@@ -123,7 +123,7 @@ __device__ __forceinline__ void batch_block_item(float* __restrict__ u, const fl
     const int r0 = p * a.b, c0 = q * a.b;
     const int r1 = min(r0 + a.b, im.H), c1 = min(c0 + a.b, im.W);
     CoarseArgs ca{LAZY ? a.partials + a.part_off[img] : nullptr, a.nchunk, LAZY ? a.cpend + a.pend_off[img] : nullptr,
-                  nj, a.lb, nullptr, 8 * a.b};
+                  nj, nullptr, 8 * a.b};
     if (im.kind == 0)
         solve_block<float, 0, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
                                                 im.alpha, M, G, gs, ca);
@@ -562,6 +562,7 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
         if (p.state_dtype != MG_F32) return bfail(nullptr, MG_E_DTYPE, "batched images use float32 state");
         if (p.fine_colours != 4) return bfail(nullptr, MG_E_INVALID, "batched images use four fine colours");
         if (p.cycle != 0) return bfail(nullptr, MG_E_INVALID, "batched images use the half V-cycle");
+        if (p.block_schedule != 0) return bfail(nullptr, MG_E_INVALID, "batched images use power-of-two blocks");
         if (p.samples != p0.samples || p.bisections != p0.bisections)
             return bfail(nullptr, MG_E_INVALID, "samples and bisections must be equal across the batch");
         if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return bfail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");

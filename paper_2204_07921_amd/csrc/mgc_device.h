@@ -45,26 +45,36 @@ __device__ __forceinline__ void stencil5(const double t[3][3], double d[5])
 
 // Value of tap (i, j) (already clamped) as the sweep sees it.  With pending
 // corrections (coarse levels apply a level's corrections lazily) the value is
-// u + c_pending of the tap's block, rounded to the state type exactly as an
-// eager update would have stored it.
+// u + c_pending of the tap's block (index k), rounded to the state type exactly
+// as an eager update would have stored it.
 template <typename T, bool LAZY>
 __device__ __forceinline__ double tap_value(const T* __restrict__ u, int W, int i, int j,
-                                            const double* __restrict__ cpend, int nj, int lb)
+                                            const double* __restrict__ cpend, int k)
 {
     const double v = (double)u[(size_t)i * W + j];
     if (!LAZY) return v;
-    const double c = cpend[(size_t)(i >> lb) * nj + (j >> lb)];
-    return (double)(T)(v + c);
+    return (double)(T)(v + cpend[k]);
+}
+
+// Index in the m_j x n_j pending corrections of the block holding tap (ci, cj)
+// (clamped into the image) of a ring pixel of block B = rows [r0, r1) x cols
+// [c0, c1), pq = p nj + q.  A ring pixel lies within one pixel of B and a tap
+// within one pixel of it, so for b >= 2 a tap above (below, left of, right of) B
+// lies in the neighbouring block on that side: comparisons give the index for
+// any block side, powers of two or not.
+__host__ __device__ __forceinline__ int tap_block(int pq, int nj, int ci, int cj, int r0, int r1, int c0, int c1)
+{
+    return pq + (ci < r0 ? -nj : (ci >= r1 ? nj : 0)) + (cj < c0 ? -1 : (cj >= c1 ? 1 : 0));
 }
 
 // Build the ring record of pixel (i, j) for block rows [r0, r1) x cols [c0, c1).
 // Pixels outside the image, and pixels whose nine clamped taps lie all inside or
 // all outside B (their curvature does not depend on c), get the zero record,
-// which contributes exactly 0 to every sum below.
+// which contributes exactly 0 to every sum below.  LAZY: pq = p nj + q (see tap_block).
 template <typename T, bool LAZY = false>
 __device__ __forceinline__ void make_ring(const T* __restrict__ u, int H, int W, int i, int j,
                                           int r0, int r1, int c0, int c1, Ring& r,
-                                          const double* __restrict__ cpend = nullptr, int nj = 0, int lb = 0)
+                                          const double* __restrict__ cpend = nullptr, int nj = 0, int pq = 0)
 {
     if (i < 0 || i >= H || j < 0 || j >= W) { zero_ring(r); return; }
     double t[3][3], m[3][3];
@@ -77,7 +87,8 @@ __device__ __forceinline__ void make_ring(const T* __restrict__ u, int H, int W,
         for (int dx = -1; dx <= 1; ++dx) {
             const int cj = clampi(j + dx, 0, W - 1);
             const bool in = rin && cj >= c0 && cj < c1;
-            t[dy + 1][dx + 1] = tap_value<T, LAZY>(u, W, ci, cj, cpend, nj, lb);
+            const int k = LAZY ? tap_block(pq, nj, ci, cj, r0, r1, c0, c1) : 0;
+            t[dy + 1][dx + 1] = tap_value<T, LAZY>(u, W, ci, cj, cpend, k);
             m[dy + 1][dx + 1] = in ? 1.0 : 0.0;
             n += in ? 1 : 0;
         }

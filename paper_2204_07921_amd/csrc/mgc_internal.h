@@ -20,15 +20,29 @@ struct CoarseScratch {
     int nchunk;         // set by launch_level_begin
     double* cpend;      // pending corrections of the level being swept, m_j x n_j
     double* cpend_alt;  // the previous coarse level's, while they are applied by the next level's sums pass
-    double* rec;        // expanded ring records of the streamed levels (b >= STREAMED_B)
+    double* rec;        // expanded ring records of the streamed levels (shape side >= STREAMED_B)
     size_t rec_cap;     // doubles in rec
 };
 
-// Block side from which the ring no longer fits in registers (one workgroup per block, records
-// rebuilt from memory or read from the record scratch at every evaluation).
+// Block side at level j (1-based): 2^(j-1) (schedule 0, nested blocks) or 2^j - 1
+// (schedule 1, the patch side of Section 2.2).  Level 1 is the pixel level in both.
+inline int block_side(int level, int schedule)
+{
+    return schedule == 1 ? (1 << level) - 1 : 1 << (level - 1);
+}
+// Smallest power of two >= b: the lane-group shape of a level is that of this side
+// (a 2^j - 1 ring has 8 fewer pixels than the 2^j one, so the same slots hold it).
+inline int shape_side(int b)
+{
+    int s = 1;
+    while (s < b) s <<= 1;
+    return s;
+}
+// Shape side from which the ring no longer fits in registers (one workgroup per block,
+// records rebuilt from memory or read from the record scratch at every evaluation).
 constexpr int STREAMED_B = 1024;
 // Doubles of record scratch the streamed levels of an H x W image with J levels need.
-size_t record_scratch_doubles(int H, int W, int J);
+size_t record_scratch_doubles(int H, int W, int J, int schedule);
 
 // b = 1: colour sweep from uin into uout (every pixel of uout is written).
 hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours);

@@ -1,7 +1,8 @@
 // Colour-sweep and energy kernels for the multigrid curvature minimisation
 // (Algorithm 3 of arXiv 2204.07921) on gfx950.
 //
-// Level j has block side b = 2^(j-1).  A colour sweep updates every block of
+// Level j has block side b = 2^(j-1) (nested blocks) or, with the paper's
+// schedule, 2^j - 1 (Section 2.2).  A colour sweep updates every block of
 // one colour; blocks of one colour at b >= 2 never share a ring pixel, so they
 // run in parallel and update u in place.  At b = 1 same-colour pixels of the
 // four-colour map do share ring pixels, so the pixel level is two-phase: every
@@ -76,17 +77,21 @@ __global__ __launch_bounds__(GROUP > 64 ? GROUP : 256) void sweep_blocks_kernel(
     }
 }
 
+// Block index of pixel coordinate i for block side b (lb = log2(b), or -1 when b
+// is not a power of two).
+__device__ __forceinline__ int side_div(int i, int b, int lb) { return lb >= 0 ? i >> lb : i / b; }
+
 // Coarse levels: partial sums of f - u, one workgroup per (block, chunk of rows).
 // partials[(p * nj + q) * nchunk + k] = sum over rows [r0 + k rows_per, ...) of
 // block (p, q); the first chunk of each block also zeroes its pending correction.
-// With cprev set, the previous coarse level's pending corrections (block side
-// 2^lbp, njp blocks per row) are first added to u, rounded to the state type as
-// the correction pass would store them.
+// With cprev set, the previous coarse level's pending corrections (block side bp,
+// njp blocks per row; lbp = log2(bp), or -1 when bp is not a power of two) are
+// first added to u, rounded to the state type as the correction pass would store them.
 template <typename T>
 __global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, const T* __restrict__ f, int H,
                                                          int W, int b, int nj, int nchunk, int rows_per,
                                                          double* __restrict__ partials, double* __restrict__ cpend,
-                                                         const double* __restrict__ cprev, int lbp, int njp)
+                                                         const double* __restrict__ cprev, int bp, int lbp, int njp)
 {
     __shared__ double lds[4];
     const int blk = blockIdx.x / nchunk, k = blockIdx.x - blk * nchunk;
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, cons
         const size_t idx = (size_t)i * W + j;
         double v = (double)u[idx];
         if (cprev) {
-            const double c = cprev[(size_t)(i >> lbp) * njp + (j >> lbp)];
+            const double c = cprev[(size_t)side_div(i, bp, lbp) * njp + side_div(j, bp, lbp)];
             if (c != 0.0) {
                 const T r = (T)(v + c);
                 u[idx] = r;
@@ -120,13 +125,13 @@ __global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, cons
 
 // End of a coarse level: u <- u + c of the pixel's block (rounded to the state type).
 template <typename T>
-__global__ __launch_bounds__(256) void apply_level_kernel(T* __restrict__ u, int H, int W, int lb, int nj,
+__global__ __launch_bounds__(256) void apply_level_kernel(T* __restrict__ u, int H, int W, int b, int lb, int nj,
                                                           const double* __restrict__ cpend)
 {
     const size_t n = (size_t)H * W;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(t / W), j = (int)(t - (size_t)i * W);
-        const double c = cpend[(size_t)(i >> lb) * nj + (j >> lb)];
+        const double c = cpend[(size_t)side_div(i, b, lb) * nj + side_div(j, b, lb)];
         if (c != 0.0) u[t] = (T)((double)u[t] + c);
     }
 }
@@ -250,8 +255,9 @@ static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, in
                                   int nbc, const CoarseArgs& ca)
 {
     // ring size of an unclipped block is 8b (lanes x records per lane = 8b); per level the
-    // fastest of the batched autotuner's candidate shapes, timed on a 1024x1024 image
-    switch (b) {
+    // fastest of the batched autotuner's candidate shapes, timed on a 1024x1024 image.  A
+    // 2^j - 1 side takes the shape of 2^j.
+    switch (shape_side(b)) {
     case 2: return launch_blocks_cfg<T, KIND, 2, 8, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 4: return launch_blocks_cfg<T, KIND, 8, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 8: return launch_blocks_cfg<T, KIND, 32, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
@@ -261,18 +267,18 @@ static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, in
     case 128: return launch_blocks_cfg<T, KIND, 256, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 256: return launch_blocks_cfg<T, KIND, 512, 4, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 512: return launch_blocks_cfg<T, KIND, 512, 8, true>(L, u, f, b, pr, pc, nbr, nbc, ca);
-    default: return launch_blocks_cfg<T, KIND, 1024, 0, true>(L, u, f, b, pr, pc, nbr, nbc, ca);   // b >= STREAMED_B
+    default: return launch_blocks_cfg<T, KIND, 1024, 0, true>(L, u, f, b, pr, pc, nbr, nbc, ca);   // shape side >= STREAMED_B
     }
 }
 
-bool level_is_lazy(int b) { return b >= 64; }
+bool level_is_lazy(int b) { return shape_side(b) >= 64; }
 
-size_t record_scratch_doubles(int H, int W, int J)
+size_t record_scratch_doubles(int H, int W, int J, int schedule)
 {
     size_t need = 0;
     for (int level = 2; level <= J; ++level) {
-        const int b = 1 << (level - 1);
-        if (b < STREAMED_B) continue;
+        const int b = block_side(level, schedule);
+        if (shape_side(b) < STREAMED_B) continue;
         const size_t mj = (size_t)(H + b - 1) / b, nj = (size_t)(W + b - 1) / b;
         const size_t per_colour = ((mj + 1) / 2) * ((nj + 1) / 2);   // colour 0 has the most blocks
         const size_t n = per_colour * 7 * (size_t)(8 * b);
@@ -286,10 +292,9 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
     const int pr = colour >> 1, pc = colour & 1;
     const int mj = (L.H + b - 1) / b, nj = (L.W + b - 1) / b;
     const int nbr = (mj - pr + 1) / 2, nbc = (nj - pc + 1) / 2;
-    CoarseArgs ca{cs.partials, cs.nchunk, cs.cpend, nj, 0, nullptr, 8 * b};
-    while ((1 << ca.lb) < b) ++ca.lb;
+    CoarseArgs ca{cs.partials, cs.nchunk, cs.cpend, nj, nullptr, 8 * b};
     // streamed levels keep their expanded records in memory when the scratch holds a region per block
-    if (b >= STREAMED_B && (size_t)nbr * nbc * 7 * (size_t)(8 * b) <= cs.rec_cap) ca.rec = cs.rec;
+    if (shape_side(b) >= STREAMED_B && (size_t)nbr * nbc * 7 * (size_t)(8 * b) <= cs.rec_cap) ca.rec = cs.rec;
     if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)
                              : launch_blocks_t<double, 0>(L, u, f, b, pr, pc, nbr, nbc, ca);
     return L.kind ? launch_blocks_t<float, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)
@@ -307,11 +312,12 @@ void coarse_geometry(int H, int W, int b, int* nblocks, int* nchunk, int* rows_p
     *nblocks = mj * nj;
 }
 
+// log2(b) for a power of two, -1 otherwise
 static int log2i(int b)
 {
     int lb = 0;
     while ((1 << lb) < b) ++lb;
-    return lb;
+    return (1 << lb) == b ? lb : -1;
 }
 
 hipError_t launch_level_begin(const LaunchCtx& L, void* u, const void* f, int b, CoarseScratch& cs, int prev_b)
@@ -333,10 +339,10 @@ hipError_t launch_level_begin(const LaunchCtx& L, void* u, const void* f, int b,
     dim3 grid((unsigned)nblocks * nchunk), block(256);
     if (L.f64)
         hipLaunchKernelGGL(block_sums_kernel<double>, grid, block, 0, L.stream, (double*)u, (const double*)f,
-                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials, cs.cpend, cprev, lbp, njp);
+                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials, cs.cpend, cprev, prev_b, lbp, njp);
     else
         hipLaunchKernelGGL(block_sums_kernel<float>, grid, block, 0, L.stream, (float*)u, (const float*)f,
-                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials, cs.cpend, cprev, lbp, njp);
+                           L.H, L.W, b, nj, nchunk, rows_per, cs.partials, cs.cpend, cprev, prev_b, lbp, njp);
     return hipGetLastError();
 }
 
@@ -349,10 +355,10 @@ hipError_t launch_level_end(const LaunchCtx& L, void* u, int b, const CoarseScra
     if (g > 4096) g = 4096;
     if (L.f64)
         hipLaunchKernelGGL(apply_level_kernel<double>, dim3((unsigned)g), dim3(256), 0, L.stream, (double*)u, L.H, L.W,
-                           lb, nj, (const double*)cs.cpend);
+                           b, lb, nj, (const double*)cs.cpend);
     else
         hipLaunchKernelGGL(apply_level_kernel<float>, dim3((unsigned)g), dim3(256), 0, L.stream, (float*)u, L.H, L.W,
-                           lb, nj, (const double*)cs.cpend);
+                           b, lb, nj, (const double*)cs.cpend);
     return hipGetLastError();
 }
 

@@ -78,6 +78,8 @@ mgc::LaunchCtx launch_ctx(const mg_curv_ctx* c)
 
 int colours_at(const mg_curv_ctx* c, int level) { return (level == 1 && c->P.fine_colours == 9) ? 9 : 4; }
 
+int side_at(const mg_curv_ctx* c, int level) { return mgc::block_side(level, c->P.block_schedule); }
+
 mg_status check_buffers(mg_curv_ctx* ctx, const void* u, const void* f)
 {
     if (!ctx) return MG_E_INVALID;
@@ -101,7 +103,7 @@ mg_status sweep(mg_curv_ctx* ctx, void* u, const void* f, int level, int colour)
         if (e != hipSuccess) return hip_fail(ctx, e, "pixel sweep copy");
         return MG_OK;
     }
-    const int b = 1 << (level - 1);
+    const int b = side_at(ctx, level);
     const bool lazy = mgc::level_is_lazy(b);
     if (lazy && (e = mgc::launch_level_begin(L, u, f, b, ctx->coarse)) != hipSuccess) return hip_fail(ctx, e, "level begin");
     e = mgc::launch_sweep_blocks(L, u, f, b, colour, ctx->coarse);
@@ -133,7 +135,7 @@ mg_status level_sweeps(mg_curv_ctx* ctx, void* u, const void* f, int level, int 
         }
         return MG_OK;
     }
-    const int b = 1 << (level - 1);
+    const int b = side_at(ctx, level);
     const bool lazy = mgc::level_is_lazy(b);
     if (lazy && (e = mgc::launch_level_begin(L, u, f, b, ctx->coarse, prev_b)) != hipSuccess)
         return hip_fail(ctx, e, "level begin");
@@ -159,8 +161,8 @@ mg_status vcycle(mg_curv_ctx* ctx, void* u, const void* f)
         for (int level = ctx->J - 1; level >= 1; --level) order[n++] = level;
     int pending = 0;
     for (int k = 0; k < n; ++k) {
-        const int level = order[k], b = 1 << (level - 1);
-        const bool defer = mgc::level_is_lazy(b) && k + 1 < n && mgc::level_is_lazy(1 << (order[k + 1] - 1));
+        const int level = order[k], b = side_at(ctx, level);
+        const bool defer = mgc::level_is_lazy(b) && k + 1 < n && mgc::level_is_lazy(side_at(ctx, order[k + 1]));
         mg_status st = level_sweeps(ctx, u, f, level, pending, defer);
         if (st != MG_OK) return st;
         pending = defer ? b : 0;
@@ -199,6 +201,7 @@ void mg_curv_default_params(mg_curv_params* p, int32_t height, int32_t width)
     p->samples = 16;
     p->bisections = 32;
     p->cycle = 0;
+    p->block_schedule = 0;
 }
 
 mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_ctx** out)
@@ -216,6 +219,8 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return fail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");
     if (p.bisections < 0 || p.bisections > 64) return fail(nullptr, MG_E_INVALID, "bisections must be in [0, 64]");
     if (p.cycle != 0 && p.cycle != 1) return fail(nullptr, MG_E_INVALID, "cycle must be 0 (half) or 1 (full)");
+    if (p.block_schedule != 0 && p.block_schedule != 1)
+        return fail(nullptr, MG_E_INVALID, "block_schedule must be 0 (2^(j-1)) or 1 (2^j - 1)");
     const int Jmax = auto_levels(p.height, p.width) + 1;
     if (p.levels < 0 || p.levels > Jmax) return fail(nullptr, MG_E_INVALID, "levels must be in [0, %d]", Jmax);
 
@@ -241,14 +246,14 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     const int np = mgc::energy_partials_count(p.height, p.width);
     size_t n_part = 1, n_pend = 1;
     for (int level = 2; level <= c->J; ++level) {
-        const int b = 1 << (level - 1);
+        const int b = side_at(c, level);
         if (!mgc::level_is_lazy(b)) continue;
         int nblocks, nchunk, rows_per;
         mgc::coarse_geometry(p.height, p.width, b, &nblocks, &nchunk, &rows_per);
         if ((size_t)nblocks * nchunk > n_part) n_part = (size_t)nblocks * nchunk;
         if ((size_t)nblocks > n_pend) n_pend = (size_t)nblocks;
     }
-    const size_t n_rec = mgc::record_scratch_doubles(p.height, p.width, c->J);
+    const size_t n_rec = mgc::record_scratch_doubles(p.height, p.width, c->J, p.block_schedule);
     c->coarse.rec_cap = n_rec;
     if (hipMalloc(&c->pingpong, nb) != hipSuccess || hipMalloc((void**)&c->partials, sizeof(double) * np) != hipSuccess ||
         hipMalloc((void**)&c->coarse.partials, sizeof(double) * n_part) != hipSuccess ||

@@ -386,7 +386,6 @@ struct CoarseArgs {
     int nchunk;
     double* cpend;           // m_j x n_j pending corrections of this level
     int nj;
-    int lb;                  // log2(b)
     double* rec;             // RPL = 0: this block's region for its expanded ring records, or null
     int rec_stride;          // records per coefficient row of a region (8b)
 };
@@ -411,6 +410,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
     // the group total of rsum (and with it f*) is taken after the ring records are built, so the
     // loads of both are in flight together
     const double s = (double)h * (double)w;
+    const int pq = p * ca.nj + q;   // lazy levels: this block's pending correction
     const RingBand band = ring_band(H, W, r0, r1, c0, c1);
     const int ncand = band.n;
 
@@ -424,7 +424,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             if (k < ncand) {
                 int i, j;
                 band_at(band, k, i, j);
-                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, ca.lb);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, pq);
             } else {
                 zero_ring(r);
             }
@@ -461,7 +461,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             Ring rr;
             PolyRing<KIND> pr;
             band_at(band, kk, i, j);
-            make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
+            make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, pq);
             make_poly<KIND>(rr, pr);
             store_poly<KIND>(ca.rec, ca.rec_stride, kk, pr);
         }
@@ -498,7 +498,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
                 Ring rr;
                 PolyRing<KIND> pr;
                 band_at(band, kk, i, j);
-                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, pq);
                 make_poly<KIND>(rr, pr);
 #pragma unroll
                 for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(pr, cs[k]);
@@ -511,7 +511,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
                 Ring rr;
                 PolyRing<KIND> pr;
                 band_at(band, kk, i, j);
-                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, ca.lb);
+                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, pq);
                 make_poly<KIND>(rr, pr);
                 acc += dabs_poly<KIND>(pr, c);
             }

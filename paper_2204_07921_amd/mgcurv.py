@@ -26,7 +26,7 @@ class MgCurvParams(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
                 ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
                 ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32),
-                ("cycle", C.c_int32)]
+                ("cycle", C.c_int32), ("block_schedule", C.c_int32)]
 
 
 class MgFbsParams(C.Structure):
@@ -285,11 +285,12 @@ class Solver:
 
     def __init__(self, height: int, width: int, alpha: float = 20.0, kind: int = MG_CURV_MEAN,
                  levels: int = 0, dtype=torch.float32, fine_colours: int = 4, samples: int = 16,
-                 bisections: int = 32, stream=None, cycle: int = 0):
+                 bisections: int = 32, stream=None, cycle: int = 0, block_schedule: int = 0):
         self.params = default_params(height, width, alpha=float(alpha), curvature=int(kind), levels=int(levels),
                                      state_dtype=MG_F64 if dtype == torch.float64 else MG_F32,
                                      fine_colours=int(fine_colours), samples=int(samples),
-                                     bisections=int(bisections), cycle=int(cycle))
+                                     bisections=int(bisections), cycle=int(cycle),
+                                     block_schedule=int(block_schedule))
         self.dtype = dtype
         self.ctx = mg_curv_init(self.params, stream)
         self.levels = lib.mg_curv_levels(self.ctx)

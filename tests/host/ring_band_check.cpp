@@ -1,7 +1,9 @@
 // Host check of the block-ring enumeration used by the colour sweeps: for every block of every
-// image up to 23 x 23 and block sides 2..16, the candidates listed by ring_band / band_at lie
-// inside the image, are distinct, number at most 8b, and include every ring pixel, i.e. every
-// pixel whose nine clamped taps lie partly inside and partly outside the block (brute force).
+// image up to 23 x 23 and block sides 2..16 (powers of two and 2^j - 1), the candidates listed by
+// ring_band / band_at lie inside the image, are distinct, number at most 8b, and include every ring
+// pixel, i.e. every pixel whose nine clamped taps lie partly inside and partly outside the block
+// (brute force).  For every candidate's clamped taps, tap_block (the coarse levels' lookup of a
+// tap's pending correction) equals the block index by division.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -29,28 +31,35 @@ int main()
     long cases = 0, bad = 0;
     for (int H = 1; H <= 23; ++H)
         for (int W = 1; W <= 23; ++W)
-            for (int b = 2; b <= 16; b *= 2)
+            for (int b : {2, 3, 4, 7, 8, 15, 16})
                 for (int r0 = 0; r0 < H; r0 += b)
                     for (int c0 = 0; c0 < W; c0 += b) {
                         const int r1 = r0 + b < H ? r0 + b : H, c1 = c0 + b < W ? c0 + b : W;
+                        const int nj = (W + b - 1) / b, pq = (r0 / b) * nj + c0 / b;
                         const mgc::RingBand B = mgc::ring_band(H, W, r0, r1, c0, c1);
                         std::set<std::pair<int, int>> got;
-                        bool dup = false, outside = false;
+                        bool dup = false, outside = false, index = true;
                         for (int k = 0; k < B.n; ++k) {
                             int i, j;
                             mgc::band_at(B, k, i, j);
                             outside = outside || i < 0 || i >= H || j < 0 || j >= W;
                             dup = dup || !got.insert({i, j}).second;
+                            for (int dy = -1; dy <= 1; ++dy)
+                                for (int dx = -1; dx <= 1; ++dx) {
+                                    const int ci = clampi_h(i + dy, 0, H - 1), cj = clampi_h(j + dx, 0, W - 1);
+                                    if (mgc::tap_block(pq, nj, ci, cj, r0, r1, c0, c1) != (ci / b) * nj + cj / b)
+                                        index = false;
+                                }
                         }
                         bool cover = true;
                         for (int i = r0 - 2; i <= r1 + 1; ++i)
                             for (int j = c0 - 2; j <= c1 + 1; ++j)
                                 if (is_ring(H, W, i, j, r0, r1, c0, c1) && !got.count({i, j})) cover = false;
                         ++cases;
-                        if (dup || outside || !cover || B.n > 8 * b) {
+                        if (dup || outside || !cover || !index || B.n > 8 * b) {
                             if (bad < 5)
-                                std::printf("H %d W %d b %d block (%d, %d): n %d dup %d outside %d cover %d\n", H, W, b,
-                                            r0, c0, B.n, dup, outside, cover);
+                                std::printf("H %d W %d b %d block (%d, %d): n %d dup %d outside %d cover %d index %d\n",
+                                            H, W, b, r0, c0, B.n, dup, outside, cover, index);
                             ++bad;
                         }
                     }

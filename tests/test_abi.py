@@ -17,7 +17,7 @@ class Params(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("alpha", C.c_double),
                 ("curvature", C.c_int32), ("levels", C.c_int32), ("state_dtype", C.c_int32),
                 ("fine_colours", C.c_int32), ("samples", C.c_int32), ("bisections", C.c_int32),
-                ("cycle", C.c_int32)]
+                ("cycle", C.c_int32), ("block_schedule", C.c_int32)]
 
 
 @pytest.fixture(scope="module")
@@ -59,13 +59,14 @@ def test_params_struct_layout(lib):
     p = Params()
     lib.mg_curv_default_params(C.byref(p), 64, 48)
     assert (p.height, p.width, p.alpha, p.curvature, p.levels, p.state_dtype) == (64, 48, 20.0, 0, 0, 0)
-    assert (p.fine_colours, p.samples, p.bisections, p.cycle) == (4, 16, 32, 0)
+    assert (p.fine_colours, p.samples, p.bisections, p.cycle, p.block_schedule) == (4, 16, 32, 0, 0)
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("height", 1, -2), ("width", 0, -2), ("alpha", 0.0, -1), ("alpha", float("nan"), -1), ("cycle", 2, -1),
     ("alpha", float("inf"), -1), ("curvature", 2, -1), ("state_dtype", 7, -3), ("fine_colours", 5, -1),
     ("samples", 3, -1), ("samples", 0, -1), ("bisections", -1, -1), ("bisections", 65, -1), ("levels", 99, -1),
+    ("block_schedule", 2, -1), ("block_schedule", -1, -1),
 ])
 def test_invalid_params_rejected_before_device(lib, field, value, status):
     p = Params()
@@ -115,7 +116,7 @@ def _batch_params(lib, shapes, **over):
 
 @pytest.mark.parametrize("over,status", [
     ({"state_dtype": 1}, -3), ({"fine_colours": 9}, -1), ({"height": 1}, -2), ({"alpha": -1.0}, -1),
-    ({"curvature": 5}, -1),
+    ({"curvature": 5}, -1), ({"block_schedule": 1}, -1),
 ])
 def test_batch_invalid_params(lib, over, status):
     lib.mg_curv_batch_init.restype = C.c_int

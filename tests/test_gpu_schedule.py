@@ -1,0 +1,186 @@
+"""GPU parity of the paper's block schedule (Section 2.2: block side 2^j - 1 at level j) against the
+FP64 CPU oracle with the same schedule.
+
+Blocks of side 2^j - 1 are not nested: a level's blocks straddle those of the next one, every ring
+holds 8 fewer pixels than the power-of-two shape the level borrows, and the coarse levels (side 63
+and up) look up pending corrections of neighbouring blocks whose side is not a power of two.  The
+tolerances are those of test_gpu_parity.py: FP64 state 1e-10 per block correction, float state the
+same rounded block values as the float-state oracle (or an equal local minimum where the arg min
+is ill-conditioned).
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import noisy_image
+from tests.parity_helpers import _check_sweep_against_oracle
+
+pytestmark = pytest.mark.gpu
+
+THREADS = 8
+PAPER = 1   # block_schedule: side 2^j - 1
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2204_07921_amd import mgcurv
+    return mgcurv
+
+
+def dev(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _f_and_u(h, w, seed, sigma, dtype, perturb=0.0):
+    f, _ = noisy_image(h, w, seed, sigma, dtype=np.float32 if dtype == torch.float32 else np.float64)
+    f = f.astype(np.float64)
+    u = f.copy()
+    if perturb:
+        rng = np.random.default_rng(seed + 77)
+        u = u + perturb * rng.standard_normal(u.shape)
+        if dtype == torch.float32:
+            u = u.astype(np.float32).astype(np.float64)
+    return f, u
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_every_sweep_ragged(mg, orc, kind, dtype):
+    """45 x 37, J = 6 (sides 1, 3, 7, 15, 31, 63): every level and colour from the same state,
+    clipped blocks at every level, and a single lazily applied block at side 63."""
+    h, w = 45, 37
+    f, u0 = _f_and_u(h, w, 5, 0.1, dtype, perturb=0.05)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype, block_schedule=PAPER)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=(dtype == torch.float32), threads=THREADS, schedule=PAPER)
+    assert s.levels == o.levels == 6
+    assert [o.block_side(j) for j in range(1, 7)] == [1, 3, 7, 15, 31, 63]
+    fd = dev(f, dtype)
+    for level in range(1, o.levels + 1):
+        for colour in range(4):
+            _case(f"schedule sweep kind={kind} {dtype} level={level} colour={colour}")
+            ug = dev(u0, dtype)
+            s.sweep(ug, fd, level, colour)
+            _, n_equal = _check_sweep_against_oracle(o, f, u0, host(ug), level, colour, fp64=dtype == torch.float64)
+            assert n_equal <= 1, (level, colour, n_equal)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_coarse_levels_sweep_by_sweep(mg, orc, kind, dtype):
+    """300 x 260, J = 9: the lazily applied levels (sides 63, 127, 255, 511) colour after colour,
+    each colour seeing the earlier colours' pending corrections of neighbouring blocks; then the
+    same four colours through one mg_curv_level call."""
+    h, w = 300, 260
+    f, u0 = _f_and_u(h, w, 8, 0.1, dtype, perturb=0.05)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype, block_schedule=PAPER)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=(dtype == torch.float32), threads=THREADS, schedule=PAPER)
+    fd = dev(f, dtype)
+    for level in range(2, o.levels + 1):
+        ug = dev(u0, dtype)
+        before = u0.copy()
+        for colour in range(4):
+            _case(f"schedule coarse {h}x{w} kind={kind} {dtype} level={level} colour={colour}")
+            s.sweep(ug, fd, level, colour)
+            after = host(ug)
+            _, n_equal = _check_sweep_against_oracle(o, f, before, after, level, colour, fp64=dtype == torch.float64)
+            assert n_equal <= 1, (level, colour, n_equal)
+            before = after
+        ul = dev(u0, dtype)
+        s.level(ul, fd, level)
+        assert torch.equal(ul, ug), level
+
+
+@pytest.mark.parametrize("cycle", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_vcycles_match_levels_and_oracle(mg, orc, kind, cycle):
+    """200 x 170, J = 8, float state: the V-cycle call (coarse levels hand their corrections to the
+    next level's sums pass, across blocks that do not nest) equals the levels run one call at a time
+    bit for bit, and three V-cycles match the float-state oracle's."""
+    h, w = 200, 170
+    _case(f"schedule vcycles kind={kind} cycle={cycle}")
+    f, _ = _f_and_u(h, w, 12, 0.1, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=torch.float32, cycle=cycle, block_schedule=PAPER)
+    J = s.levels
+    fd = dev(f, torch.float32)
+    ua, ub = dev(f, torch.float32), dev(f, torch.float32)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=True, threads=THREADS, cycle=cycle, schedule=PAPER)
+    uo = f.copy()
+    order = list(range(1, J + 1)) + (list(range(J - 1, 0, -1)) if cycle else [])
+    for rep in range(3):
+        s.vcycle(ua, fd)
+        for level in order:
+            s.level(ub, fd, level)
+        assert torch.equal(ua, ub), rep
+        o.vcycle(uo, f)
+        du = np.max(np.abs(host(ua) - uo))
+        print(f"V-cycle {rep + 1}: max |du| vs oracle {du:.3e}")
+        assert du <= 1e-6
+    pow2 = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=torch.float32, cycle=cycle)
+    up = dev(f, torch.float32)
+    pow2.vcycle(up, fd)
+    assert not torch.equal(up, dev(f, torch.float32))
+
+
+def test_relerr_stop_matches_oracle(mg, orc):
+    """relErr(u) stop (Section 4) on the paper's schedule with the full V-cycle: same number of
+    V-cycles, final energy and state as the float-state oracle."""
+    h, w = 80, 72
+    _case("schedule relErr stop")
+    f, _ = _f_and_u(h, w, 9, 0.08, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=0, dtype=torch.float32, cycle=1, block_schedule=PAPER)
+    ug = dev(f, torch.float32)
+    res = s.solve_rule(ug, dev(f, torch.float32), 1e-3, max_vcycles=200, stop=mg.MG_STOP_RELERR_U)
+    o = orc.Oracle(h, w, 20.0, 0, round_f32=True, threads=THREADS, cycle=1, schedule=PAPER)
+    uo = f.copy()
+    n, trace = o.solve_rule(uo, f, 1e-3, max_vcycles=200, stop=1)
+    print(f"gpu vcycles={res['vcycles']} oracle={n}")
+    assert res["status"] == 0
+    assert res["vcycles"] == n
+    assert abs(res["energy"] - trace[-1]) <= 1e-9 * trace[-1]
+    assert np.max(np.abs(host(ug) - uo)) <= 1e-6
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_sampled_parity_1024(mg, orc, kind):
+    """1024 x 1024, J = 10 (sides up to 1023, whose ring streams from the record scratch), float
+    state, after two V-cycles: sampled blocks of one colour per level against the oracle's local
+    solve on the same state."""
+    h = w = 1024
+    f, _ = _f_and_u(h, w, 0, 0.1, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=torch.float32, block_schedule=PAPER)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=True, schedule=PAPER)
+    assert s.levels == o.levels == 10
+    fd = dev(f, torch.float32)
+    ug = dev(f, torch.float32)
+    for _ in range(2):
+        s.vcycle(ug, fd)
+    rng = np.random.default_rng(kind)
+    for level in (1, 2, 3, 6, 9, 10):
+        colour = int(rng.integers(0, 4))
+        _case(f"schedule sampled 1024 kind={kind} level={level} colour={colour}")
+        before = host(ug)
+        s.sweep(ug, fd, level, colour)
+        after = host(ug)
+        m, n = o.grid(level)
+        cand = [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
+        pick = rng.choice(len(cand), size=min(12, len(cand)), replace=False)
+        for k in pick:
+            p, q = cand[int(k)]
+            r0, r1, c0, c1 = o.block_bounds(level, p, q)
+            info = o.local_solve(before, f, (r0, r1, c0, c1))
+            expect = (before[r0:r1, c0:c1] + info.c).astype(np.float32).astype(np.float64)
+            err = np.max(np.abs(after[r0:r1, c0:c1] - expect))
+            assert err <= 2.5e-7, (level, p, q, err, info.c)
+        untouched = np.ones((h, w), dtype=bool)
+        for p, q in cand:
+            r0, r1, c0, c1 = o.block_bounds(level, p, q)
+            untouched[r0:r1, c0:c1] = False
+        assert np.array_equal(after[untouched], before[untouched]), level
