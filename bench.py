@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--no-warm", action="store_true", help="skip the CNN warm-start comparison")
     ap.add_argument("--no-fbs", action="store_true", help="skip the paper's own local step (FBS) measurement")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction (b = A u + noise) measurement")
+    ap.add_argument("--no-schedule", action="store_true",
+                    help="skip the paper's 2^j - 1 block schedule measurement")
     ap.add_argument("--recon-only", action="store_true",
                     help="run only the reconstruction measurement and print its JSON (for profiling its kernels)")
     ap.add_argument("--fbs-only", action="store_true",
@@ -275,6 +277,38 @@ def recon_measure(steps: int, warmup: int) -> dict:
     return out
 
 
+def schedule_measure(fd, stream, kind: int, steps: int, warmup: int) -> dict:
+    """The same image on the paper's block schedule (side 2^j - 1, Section 2.2) next to the nested
+    power-of-two one: V-cycle rate, and solves from u = f to relErr(u) < 1e-4 (the rule of the
+    paper's Tables 2-3)."""
+    import torch
+    from paper_2204_07921_amd import mgcurv
+    out = {}
+    for sched, name in ((1, "paper_2^j-1"), (0, "nested_2^(j-1)")):
+        s = mgcurv.Solver(H, W, alpha=ALPHA, kind=kind, dtype=torch.float32, stream=stream, block_schedule=sched)
+        u = fd.clone()
+        for _ in range(warmup):
+            s.vcycle(u, fd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.vcycle(u, fd)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        uu = fd.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = s.solve_rule(uu, fd, 1e-4, max_vcycles=400, stop=mgcurv.MG_STOP_RELERR_U)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        out[name] = {"levels": s.levels, "value": round(H * W / dt / 1e6, 3), "unit": "Mpixel*V-cycles/s",
+                     "ms_per_vcycle": round(dt * 1e3, 4),
+                     "relerr_1e-4": {"seconds": round(el, 4), "vcycles": res["vcycles"], "energy": res["energy"],
+                                     "status": res["status"]}}
+        s.close()
+    return out
+
+
 def cpu_baseline(f64: np.ndarray, kind: int, vcycles: int) -> dict:
     import oracle
     threads = min(os.cpu_count() or 1, 16)
@@ -401,6 +435,8 @@ def main():
         "energy_last": energies[-1],
         "time_to_tol": solves,
     }
+    if not args.no_schedule:
+        out["block_schedule"] = schedule_measure(fd, stream, args.kind, args.steps, args.warmup)
     if not args.no_warm and "mean" in solves:
         out["warm_start"] = warm_start_measure(fd, solves["mean"], args.warm_batch)
     if not args.no_batch:
