@@ -225,7 +225,11 @@ mg_status mg_curv_batch_tune(mg_curv_batch *b, void *u, const void *f, int32_t r
 
 /* Inspect / force the lane-group shape (group lanes, ring records per lane)
  * and persistent grid of one level.  set_config rejects shapes that are not
- * compiled for that level. */
+ * compiled for that level.  At level 2 (b = 2), records = -1 with group = 4
+ * (or 2) is the mirrored form: blocks off the image border read their ring as
+ * four mirrored quadrants with constant slopes (one or two quadrants of four
+ * records per lane), border blocks use the general (4, 4) (or (2, 8))
+ * records; (4, -1) is that level's default. */
 int32_t mg_curv_batch_config(const mg_curv_batch *b, int32_t level, int32_t *group, int32_t *records, int32_t *grid);
 mg_status mg_curv_batch_set_config(mg_curv_batch *b, int32_t level, int32_t group, int32_t records, int32_t grid);
 

@@ -116,20 +116,29 @@ __device__ __forceinline__ void batch_block_item(float* __restrict__ u, const fl
                                                  const BatchLevelArgs& a, int M, int G, const GSum& gs)
 {
     const int mj = (im.H + a.b - 1) >> a.lb, nj = (im.W + a.b - 1) >> a.lb;
-    (void)mj;
-    const int nbc = (nj - a.pc + 1) / 2;
-    const int bi = local / nbc, bj = local - bi * nbc;
-    const int p = 2 * bi + a.pr, q = 2 * bj + a.pc;
-    const int r0 = p * a.b, c0 = q * a.b;
-    const int r1 = min(r0 + a.b, im.H), c1 = min(c0 + a.b, im.W);
-    CoarseArgs ca{LAZY ? a.partials + a.part_off[img] : nullptr, a.nchunk, LAZY ? a.cpend + a.pend_off[img] : nullptr,
-                  nj, nullptr, 8 * a.b};
-    if (im.kind == 0)
-        solve_block<float, 0, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
-                                                im.alpha, M, G, gs, ca);
-    else
-        solve_block<float, 1, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
-                                                im.alpha, M, G, gs, ca);
+    if constexpr (RPL < 0) {   // b = 2, mirrored form off the image border (GROUP = 2 or 4)
+        const Split2 S = split2(mj, nj, a.pr, a.pc);
+        if (im.kind == 0)
+            solve_b2_item<float, 0, GROUP>(u + im.off, f + im.off, im.H, im.W, a.pr, a.pc, S, local, lane, im.alpha,
+                                           M, G);
+        else
+            solve_b2_item<float, 1, GROUP>(u + im.off, f + im.off, im.H, im.W, a.pr, a.pc, S, local, lane, im.alpha,
+                                           M, G);
+    } else {
+        const int nbc = (nj - a.pc + 1) / 2;
+        const int bi = local / nbc, bj = local - bi * nbc;
+        const int p = 2 * bi + a.pr, q = 2 * bj + a.pc;
+        const int r0 = p * a.b, c0 = q * a.b;
+        const int r1 = min(r0 + a.b, im.H), c1 = min(c0 + a.b, im.W);
+        CoarseArgs ca{LAZY ? a.partials + a.part_off[img] : nullptr, a.nchunk, LAZY ? a.cpend + a.pend_off[img] : nullptr,
+                      nj, nullptr, 8 * a.b};
+        if (im.kind == 0)
+            solve_block<float, 0, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
+                                                    im.alpha, M, G, gs, ca);
+        else
+            solve_block<float, 1, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
+                                                    im.alpha, M, G, gs, ca);
+    }
 }
 
 template <int GROUP, int RPL, bool LAZY>
@@ -268,7 +277,7 @@ static std::vector<BlockCfg> block_candidates(int b)
 {
     // the first entry is the single-image path's shape for this block side
     switch (b) {
-    case 2: return {{2, 8}, {4, 4}, {16, 1}, {8, 2}};
+    case 2: return {{4, -1}, {2, -1}, {2, 8}, {4, 4}, {16, 1}, {8, 2}};   // -1: mirrored form off the border
     case 4: return {{8, 4}, {32, 1}, {16, 2}, {4, 8}};
     case 8: return {{32, 2}, {16, 4}, {64, 1}, {8, 8}};
     case 16: return {{64, 2}, {32, 4}, {16, 8}};
@@ -300,6 +309,7 @@ static hipError_t launch_batch_blocks(hipStream_t s, BlockCfg cfg, int grid, flo
 #define MGC_CASE(GR, RP, LZ)                                                                                     \
     if (cfg.group == GR && cfg.rpl == RP && lazy == LZ)                                                          \
         return launch_bb<GR, RP, LZ>(s, grid, u, f, imgs, order, cum, n, total, active, a, M, G);
+    MGC_CASE(2, -1, false) MGC_CASE(4, -1, false)
     MGC_CASE(16, 1, false) MGC_CASE(8, 2, false) MGC_CASE(4, 4, false) MGC_CASE(2, 8, false)
     MGC_CASE(32, 1, false) MGC_CASE(16, 2, false) MGC_CASE(8, 4, false) MGC_CASE(4, 8, false)
     MGC_CASE(64, 1, false) MGC_CASE(32, 2, false) MGC_CASE(16, 4, false) MGC_CASE(8, 8, false)

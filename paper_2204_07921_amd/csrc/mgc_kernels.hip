@@ -81,6 +81,17 @@ __global__ __launch_bounds__(GROUP > 64 ? GROUP : 256) void sweep_blocks_kernel(
 // is not a power of two).
 __device__ __forceinline__ int side_div(int i, int b, int lb) { return lb >= 0 ? i >> lb : i / b; }
 
+// b = 2 (nested schedule): QL lanes per block; blocks off the image border take the
+// mirrored constant-slope form, the border blocks (numbered first) the general records.
+template <typename T, int KIND, int QL>
+__global__ __launch_bounds__(256) void sweep_b2_kernel(T* __restrict__ u, const T* __restrict__ f, int H, int W,
+                                                       int pr, int pc, Split2 S, double alpha, int M, int G)
+{
+    const int k = (blockIdx.x * blockDim.x + threadIdx.x) / QL;
+    if (k >= S.nbr * S.nbc) return;   // all lanes of a group exit together
+    solve_b2_item<T, KIND, QL>(u, f, H, W, pr, pc, S, k, threadIdx.x & (QL - 1), alpha, M, G);
+}
+
 // Coarse levels: partial sums of f - u, one workgroup per (block, chunk of rows).
 // partials[(p * nj + q) * nchunk + k] = sum over rows [r0 + k rows_per, ...) of
 // block (p, q); the first chunk of each block also zeroes its pending correction.
@@ -251,14 +262,26 @@ static hipError_t launch_blocks_cfg(const LaunchCtx& L, void* u, const void* f, 
 }
 
 template <typename T, int KIND>
+static hipError_t launch_b2(const LaunchCtx& L, void* u, const void* f, int pr, int pc)
+{
+    constexpr int QL = 4;   // one quadrant per lane: four waves per SIMD at 1024 x 1024 (two lanes: two)
+    const Split2 S = split2((L.H + 1) / 2, (L.W + 1) / 2, pr, pc);
+    const size_t threads = (size_t)S.nbr * S.nbc * QL;
+    if (threads == 0) return hipSuccess;
+    hipLaunchKernelGGL((sweep_b2_kernel<T, KIND, QL>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, L.stream,
+                       (T*)u, (const T*)f, L.H, L.W, pr, pc, S, L.alpha, L.M, L.G);
+    return hipGetLastError();
+}
+
+template <typename T, int KIND>
 static hipError_t launch_blocks_t(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr,
                                   int nbc, const CoarseArgs& ca)
 {
+    if (b == 2) return launch_b2<T, KIND>(L, u, f, pr, pc);
     // ring size of an unclipped block is 8b (lanes x records per lane = 8b); per level the
     // fastest of the batched autotuner's candidate shapes, timed on a 1024x1024 image.  A
     // 2^j - 1 side takes the shape of 2^j.
     switch (shape_side(b)) {
-    case 2: return launch_blocks_cfg<T, KIND, 2, 8, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 4: return launch_blocks_cfg<T, KIND, 8, 4, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 8: return launch_blocks_cfg<T, KIND, 32, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);
     case 16: return launch_blocks_cfg<T, KIND, 64, 2, false>(L, u, f, b, pr, pc, nbr, nbc, ca);

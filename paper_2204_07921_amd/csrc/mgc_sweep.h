@@ -26,7 +26,9 @@ struct PixelRing {
     double e[4][KIND == KIND_MEAN ? 5 : 4];   // E, W, S, N: mean {w0, p, P0, A, k}, Gaussian {w0, p, D0, D1}
 };
 
-__device__ __forceinline__ void stencil_at(const double w[5][5], int r, int c, double d[5])
+// 3x3 central differences at (r, c) of a tap window with C columns
+template <int C>
+__device__ __forceinline__ void stencil_at(const double (*w)[C], int r, int c, double d[5])
 {
     d[0] = 0.5 * (w[r][c + 1] - w[r][c - 1]);
     d[1] = 0.5 * (w[r + 1][c] - w[r - 1][c]);
@@ -320,6 +322,219 @@ __device__ __forceinline__ void solve_ring_cell(const T* __restrict__ uin, T* __
 }
 
 // ---------------------------------------------------------------------------
+// Block level b = 2, blocks that touch no image border (1 <= p <= m_j - 2 and
+// 1 <= q <= n_j - 2, so no clamped tap lands in the block).
+//
+// Mirroring the image across a block's horizontal or vertical centre line maps
+// u_x, u_y, u_xy to exactly -u_x, -u_y or -u_xy (a difference of two taps
+// reversed) and keeps u_xx, u_yy, q, the mean-curvature numerator and the
+// Gaussian determinant; so every quadrant of the 4 x 4 ring, read in its own
+// mirrored frame, is the top-left quadrant.  In that frame (block = {0, 1}^2)
+// the quadrant holds four ring pixels with constant slopes:
+//   corner (-1, -1): only u_xy moves (+c/4); q is constant, so kappa is a
+//     polynomial in c (mean: linear, Gaussian: quadratic) with q folded in;
+//   top edge (-1, 0): u_y moves (+c/2), u_yy (+c), u_xy (+c/4).  With w = u_y
+//     and p = 1 + u_x^2, q = p + w^2 and, eliminating c = 2 (w - w0) from the
+//     u_x w c/2 cross term, N = P0 + p c + w (A w + k) with P0 = u_xx + p u_yy,
+//     A = u_xx - u_x, k = u_x (w0 - 2 u_xy); D = D0 + D1 c - c^2/16 with
+//     D1 = u_xx - u_xy / 2;
+//   left edge (0, -1): the same with x and y exchanged;
+//   inside (0, 0): u_x, u_y move (+c/2), u_xx, u_yy (-c), u_xy (+c/4): the
+//     general expansion in powers of c with these slopes.
+// Lane 0 takes the top two quadrants, lane 1 the bottom two (rows read in
+// reverse); each lane reads a 4 x 6 tap window once and mirrors columns for its
+// right quadrant in registers.
+// ---------------------------------------------------------------------------
+template <int KIND>
+struct QuadRing {
+    double g[KIND == KIND_MEAN ? 2 : 3];     // corner: kappa = sum_m g[m] c^m
+    double et[KIND == KIND_MEAN ? 5 : 4];    // top edge:  mean {w0, p, P0, A, k}, Gaussian {w0, p, D0, D1}
+    double el[KIND == KIND_MEAN ? 5 : 4];    // left edge: the same
+    PolyRing<KIND> in;                       // inside pixel
+};
+
+// Edge records of the quadrant: w = w0 + c/2 moves, q = p + w^2, dq/dc = w.
+template <int KIND>
+__device__ __forceinline__ void make_qedge(const double d[5], bool top, double e[])
+{
+    const double w0 = top ? d[1] : d[0];
+    const double o = top ? d[0] : d[1];
+    const double p = fma(o, o, 1.0);
+    e[0] = w0;
+    e[1] = p;
+    const double mov2 = top ? d[3] : d[2], fix2 = top ? d[2] : d[3];
+    if constexpr (KIND == KIND_MEAN) {
+        e[2] = fma(p, mov2, fix2);
+        e[3] = fix2 - o;
+        e[4] = o * fma(-2.0, d[4], w0);
+    } else {
+        e[2] = fma(d[2], d[3], -d[4] * d[4]);
+        e[3] = fma(-0.5, d[4], fix2);
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ double qedge_abs(const double e[], double c)
+{
+    const double w = fma(0.5, c, e[0]);
+    const double q = fma(w, w, e[1]);
+    const double rq = rsqrt_pos(q);
+    if constexpr (KIND == KIND_MEAN) {
+        const double num = fma(w, fma(e[3], w, e[4]), fma(e[1], c, e[2]));
+        return fabs(num) * (rq * rq * rq);
+    } else {
+        const double det = fma(fma(-0.0625, c, e[3]), c, e[2]);
+        const double r2 = rq * rq;
+        return fabs(det) * (r2 * r2);
+    }
+}
+
+// mean: N' = p + (2 A w + k) / 2, N' q - 3/2 N q';  Gaussian: D' = D1 - c/8, D' q - 2 D q'
+template <int KIND>
+__device__ __forceinline__ double qedge_dabs(const double e[], double c)
+{
+    const double w = fma(0.5, c, e[0]);
+    const double q = fma(w, w, e[1]);
+    const double rq = rsqrt_pos(q);
+    const double r2 = rq * rq;
+    if constexpr (KIND == KIND_MEAN) {
+        const double inner = fma(e[3], w, e[4]);
+        const double num = fma(w, inner, fma(e[1], c, e[2]));
+        const double dnum = fma(0.5, fma(e[3], w, inner), e[1]);
+        const double t = fma(-1.5 * num, w, dnum * q);
+        return signed_by(num, t * (r2 * r2 * rq));
+    } else {
+        const double det = fma(fma(-0.0625, c, e[3]), c, e[2]);
+        const double ddet = fma(-0.125, c, e[3]);
+        const double t = fma(-2.0 * det, w, ddet * q);
+        return signed_by(det, t * (r2 * r2 * r2));
+    }
+}
+
+// wq[y + 2][x + 2] = tap at (y, x) of the quadrant's frame, y, x in -2..1
+template <int KIND>
+__device__ __forceinline__ void make_quad(const double (&wq)[4][4], QuadRing<KIND>& R)
+{
+    double d[5];
+    stencil_at(wq, 1, 1, d);   // corner: u_xy slope +1/4
+    {
+        const double q = fma(d[0], d[0], fma(d[1], d[1], 1.0));
+        const double rq = rsqrt_pos(q);
+        if constexpr (KIND == KIND_MEAN) {
+            const double n0 = fma(fma(d[1], d[1], 1.0), d[2], fma(fma(d[0], d[0], 1.0), d[3], -2.0 * d[0] * d[1] * d[4]));
+            const double r = rq * rq * rq;
+            R.g[0] = n0 * r;
+            R.g[1] = (-0.5 * d[0] * d[1]) * r;
+        } else {
+            const double r = (rq * rq) * (rq * rq);
+            R.g[0] = fma(d[2], d[3], -d[4] * d[4]) * r;
+            R.g[1] = (-0.5 * d[4]) * r;
+            R.g[2] = -0.0625 * r;
+        }
+    }
+    stencil_at(wq, 1, 2, d);
+    make_qedge<KIND>(d, true, R.et);
+    stencil_at(wq, 2, 1, d);
+    make_qedge<KIND>(d, false, R.el);
+    Ring r;
+    stencil_at(wq, 2, 2, r.a);
+    r.b[0] = 0.5;
+    r.b[1] = 0.5;
+    r.b[2] = -1.0;
+    r.b[3] = -1.0;
+    r.b[4] = 0.25;
+    make_poly<KIND>(r, R.in);
+}
+
+template <int KIND>
+__device__ __forceinline__ double quad_abs(const QuadRing<KIND>& R, double c)
+{
+    double s;
+    if constexpr (KIND == KIND_MEAN)
+        s = fabs(fma(R.g[1], c, R.g[0]));
+    else
+        s = fabs(fma(fma(R.g[2], c, R.g[1]), c, R.g[0]));
+    s += qedge_abs<KIND>(R.et, c);
+    s += qedge_abs<KIND>(R.el, c);
+    s += abs_poly<KIND>(R.in, c);
+    return s;
+}
+
+template <int KIND>
+__device__ __forceinline__ double quad_dabs(const QuadRing<KIND>& R, double c)
+{
+    double s;
+    if constexpr (KIND == KIND_MEAN) {
+        s = signed_by(fma(R.g[1], c, R.g[0]), R.g[1]);
+    } else {
+        const double v = fma(fma(R.g[2], c, R.g[1]), c, R.g[0]);
+        s = signed_by(v, fma(R.g[2], c + c, R.g[1]));
+    }
+    s += qedge_dabs<KIND>(R.et, c);
+    s += qedge_dabs<KIND>(R.el, c);
+    s += dabs_poly<KIND>(R.in, c);
+    return s;
+}
+
+// The 2 x 2 block at (r0, c0), off the image border, on a group of QL lanes:
+// QL = 2: lane 0 the top two quadrants, lane 1 the bottom two (rows read in
+// reverse), each lane reading a 4 x 6 window and mirroring its right quadrant in
+// registers; QL = 4: one quadrant per lane (lane bit 1 mirrors rows, bit 0
+// columns), a 4 x 4 window each.
+template <typename T, int KIND, int QL>
+__device__ __forceinline__ void solve_block2_interior(T* __restrict__ u, const T* __restrict__ f, int H, int W,
+                                                      int r0, int c0, int lane, double alpha, int M, int G)
+{
+    static_assert(QL == 2 || QL == 4, "two or four lanes per block");
+    constexpr int NQ = 4 / QL;        // quadrants per lane
+    constexpr int WC = 2 + 2 * NQ;    // window columns
+    const int ybit = QL == 2 ? lane : lane >> 1, xbit = QL == 2 ? 0 : lane & 1;
+    const int sy = ybit ? -1 : 1, sx = xbit ? -1 : 1;
+    const int Y = r0 + ybit, X = c0 + xbit;   // the frame's (0, 0) of the lane's first quadrant
+    double win[4][WC];                        // rows Y + sy (a - 2), columns X + sx (b - 2)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const T* row = u + (size_t)clampi(Y + sy * (a - 2), 0, H - 1) * W;
+#pragma unroll
+        for (int b = 0; b < WC; ++b) win[a][b] = (double)row[clampi(X + sx * (b - 2), 0, W - 1)];
+    }
+    const size_t iy = (size_t)Y * W + X;
+    double rsum = (double)f[iy] - win[2][2];
+    if constexpr (NQ == 2) rsum += (double)f[iy + 1] - win[2][3];
+    QuadRing<KIND> R[NQ];
+#pragma unroll
+    for (int h = 0; h < NQ; ++h) {   // h = 1: the right quadrant, mirrored
+        double wq[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) wq[a][b] = h == 0 ? win[a][b] : win[a][5 - b];
+        make_quad<KIND>(wq, R[h]);
+    }
+    const WaveSum<QL> gs;
+    const double fs = gs(rsum) / 4.0;
+    auto Kpart = [&](const auto& cs, auto& out) {
+        constexpr int N = sizeof(out) / sizeof(double);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double v = quad_abs<KIND>(R[0], cs[k]);
+            if constexpr (NQ == 2) v += quad_abs<KIND>(R[1], cs[k]);
+            out[k] = v;
+        }
+    };
+    auto Dpart = [&](double c) {
+        double v = quad_dabs<KIND>(R[0], c);
+        if constexpr (NQ == 2) v += quad_dabs<KIND>(R[1], c);
+        return v;
+    };
+    const double cval = local_solve(Kpart, Dpart, gs, fs, alpha * 4.0, M, G);
+    if (cval != 0.0) {
+        u[iy] = (T)(win[2][2] + cval);
+        if constexpr (NQ == 2) u[iy + 1] = (T)(win[2][3] + cval);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Ring candidates of block rows [r0, r1) x cols [c0, c1) of an H x W image: the
 // pixels within distance 1 of a block side that does not lie on the image
 // border, as strips two pixels wide.  A side on the border has nothing outside
@@ -527,6 +742,76 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
             const size_t idx = (size_t)i * W + j;
             u[idx] = (T)((double)u[idx] + cval);
         }
+    }
+}
+
+// Blocks of one colour at b = 2: the colour's sub-grid is nbr x nbc, sub-block
+// (bi, bj) being block (2 bi + pr, 2 bj + pc) of the m_j x n_j grid.  Its
+// interior blocks (off the image border) form the rectangle [bi0, bi0 + nir) x
+// [bj0, bj0 + nic); the border blocks (the rest) are numbered first, so they
+// fill whole wavefronts of their own.
+struct Split2 {
+    int nbr, nbc, bi0, nir, bj0, nic, nborder;
+};
+
+__host__ __device__ __forceinline__ Split2 split2(int mj, int nj, int pr, int pc)
+{
+    Split2 S;
+    S.nbr = (mj - pr + 1) / 2;
+    S.nbc = (nj - pc + 1) / 2;
+    S.bi0 = pr == 0 ? 1 : 0;   // p = 0 is on the border
+    S.bj0 = pc == 0 ? 1 : 0;
+    const int ri = mj - 2 - pr, ci = nj - 2 - pc;   // p <= m_j - 2  <=>  bi <= (m_j - 2 - pr) / 2
+    S.nir = ri >= 0 ? ri / 2 - S.bi0 + 1 : 0;
+    S.nic = ci >= 0 ? ci / 2 - S.bj0 + 1 : 0;
+    if (S.nir < 0) S.nir = 0;
+    if (S.nic < 0) S.nic = 0;
+    if (S.nir == 0 || S.nic == 0) S.nir = S.nic = 0;
+    S.nborder = S.nbr * S.nbc - S.nir * S.nic;
+    return S;
+}
+
+__host__ __device__ __forceinline__ bool split2_at(const Split2& S, int k, int& bi, int& bj)
+{
+    if (k >= S.nborder) {
+        k -= S.nborder;
+        bi = S.bi0 + k / S.nic;
+        bj = S.bj0 + k % S.nic;
+        return true;
+    }
+    if (S.nir == 0) {   // no interior: every block is a border block
+        bi = k / S.nbc;
+        bj = k % S.nbc;
+        return false;
+    }
+    const int top = S.bi0 * S.nbc;
+    if (k < top) { bi = k / S.nbc; bj = k % S.nbc; return false; }
+    k -= top;
+    const int bot0 = S.bi0 + S.nir, bot = (S.nbr - bot0) * S.nbc;
+    if (k < bot) { bi = bot0 + k / S.nbc; bj = k % S.nbc; return false; }
+    k -= bot;
+    const int side = S.nbc - S.nic;   // border blocks per middle row (left, then right)
+    const int m = k % side;
+    bi = S.bi0 + k / side;
+    bj = m < S.bj0 ? m : S.nic + m;
+    return false;
+}
+
+// One lane of the QL-lane group solving sub-block k of a b = 2 colour.
+template <typename T, int KIND, int QL>
+__device__ __forceinline__ void solve_b2_item(T* __restrict__ u, const T* __restrict__ f, int H, int W, int pr, int pc,
+                                              const Split2& S, int k, int lane, double alpha, int M, int G)
+{
+    int bi, bj;
+    const bool interior = split2_at(S, k, bi, bj);
+    const int p = 2 * bi + pr, q = 2 * bj + pc;
+    const int r0 = 2 * p, c0 = 2 * q;
+    if (interior) {
+        solve_block2_interior<T, KIND, QL>(u, f, H, W, r0, c0, lane, alpha, M, G);
+    } else {
+        const CoarseArgs ca{nullptr, 0, nullptr, 0, nullptr, 16};
+        solve_block<T, KIND, QL, 16 / QL, false>(u, f, H, W, p, q, r0, min(r0 + 2, H), c0, min(c0 + 2, W), lane,
+                                                 alpha, M, G, WaveSum<QL>(), ca);
     }
 }
 

@@ -3,7 +3,8 @@
 // ring_band / band_at lie inside the image, are distinct, number at most 8b, and include every ring
 // pixel, i.e. every pixel whose nine clamped taps lie partly inside and partly outside the block
 // (brute force).  For every candidate's clamped taps, tap_block (the coarse levels' lookup of a
-// tap's pending correction) equals the block index by division.
+// tap's pending correction) equals the block index by division.  The b = 2 split of a colour's
+// blocks into border and interior ones (split2) is checked against its definition.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -63,6 +64,30 @@ int main()
                             ++bad;
                         }
                     }
+    // b = 2 colour split: every block of the colour exactly once, border blocks (p or q on the
+    // first or last block row or column) numbered before the interior ones
+    for (int mj = 1; mj <= 13; ++mj)
+        for (int nj = 1; nj <= 13; ++nj)
+            for (int pr = 0; pr < 2; ++pr)
+                for (int pc = 0; pc < 2; ++pc) {
+                    const mgc::Split2 S = mgc::split2(mj, nj, pr, pc);
+                    std::set<std::pair<int, int>> seen;
+                    bool ok = S.nbr == (mj - pr + 1) / 2 && S.nbc == (nj - pc + 1) / 2;
+                    for (int k = 0; k < S.nbr * S.nbc; ++k) {
+                        int bi, bj;
+                        const bool interior = mgc::split2_at(S, k, bi, bj);
+                        const int p = 2 * bi + pr, q = 2 * bj + pc;
+                        ok = ok && bi >= 0 && bi < S.nbr && bj >= 0 && bj < S.nbc && seen.insert({bi, bj}).second;
+                        ok = ok && interior == (p >= 1 && p <= mj - 2 && q >= 1 && q <= nj - 2);
+                        ok = ok && interior == (k >= S.nborder);
+                    }
+                    ok = ok && (int)seen.size() == S.nbr * S.nbc;
+                    ++cases;
+                    if (!ok) {
+                        if (bad < 5) std::printf("split2 mj %d nj %d pr %d pc %d\n", mj, nj, pr, pc);
+                        ++bad;
+                    }
+                }
     std::printf("cases %ld bad %ld\n", cases, bad);
     return bad == 0 ? 0 : 1;
 }

@@ -127,7 +127,7 @@ def test_every_compiled_shape_matches_oracle(mg, orc):
     """Force each compiled lane-group shape of a level and check that level against the oracle."""
     shapes = [(130, 150, 20.0, 0), (150, 130, 20.0, 1), (97, 64, 10.0, 0)]
     fs = _images(shapes, seed0=500)
-    cands = {2: [(4, 4), (16, 1), (8, 2), (2, 8)], 3: [(8, 4), (32, 1), (16, 2), (4, 8)],
+    cands = {2: [(2, -1), (4, -1), (4, 4), (16, 1), (8, 2), (2, 8)], 3: [(8, 4), (32, 1), (16, 2), (4, 8)],
              4: [(16, 4), (64, 1), (32, 2), (8, 8)], 5: [(32, 4), (64, 2), (16, 8)], 6: [(64, 4), (32, 8)],
              7: [(256, 2), (128, 4), (64, 8)], 8: [(256, 4), (512, 2)]}
     for level, shs in cands.items():
