@@ -82,7 +82,7 @@ typedef struct {
     int32_t block_schedule; /* block side at level j: 0: 2^(j-1), nested blocks (default);
                               1: 2^j - 1, the patch side of Section 2.2 (blocks of one
                               level then straddle those of the next).  Both are single
-                              pixels at j = 1.  Batches take 0 only. */
+                              pixels at j = 1.  Equal across a batch. */
 } mg_curv_params;
 
 typedef struct mg_curv_ctx mg_curv_ctx;
@@ -172,8 +172,8 @@ const char *mg_curv_last_error(const mg_curv_ctx *ctx);
  * algorithm above with its own level count J_i; one V-cycle runs levels
  * 1 .. max J_i, and each (level, colour) is one persistent kernel over the
  * work items of all images (images with J_i < level have none).
- * Requirements: state_dtype MG_F32 and fine_colours 4 for every image;
- * samples and bisections equal across the batch.  The batch owns a packed
+ * Requirements: state_dtype MG_F32, fine_colours 4 and cycle 0 for every
+ * image; samples, bisections and block_schedule equal across the batch.  The batch owns a packed
  * ping-pong buffer and small per-level tables; it is bound to one device and
  * stream and is not thread-safe.
  * ------------------------------------------------------------------------ */

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void batch_ring_cells_kernel(const float* __re
 }
 
 struct BatchLevelArgs {
-    int b, lb, pr, pc;
+    int b, lb, pr, pc;            // lb = log2(b), or -1 when b is not a power of two
     const double* partials;       // coarse: block partial sums
     const long long* part_off;    // per image offset into partials
     int nchunk;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void batch_block_item(float* __restrict__ u, const fl
                                                  const BatchImg& im, int img, int local, int lane,
                                                  const BatchLevelArgs& a, int M, int G, const GSum& gs)
 {
-    const int mj = (im.H + a.b - 1) >> a.lb, nj = (im.W + a.b - 1) >> a.lb;
+    const int mj = side_div(im.H + a.b - 1, a.b, a.lb), nj = side_div(im.W + a.b - 1, a.b, a.lb);
     if constexpr (RPL < 0) {   // b = 2, mirrored form off the image border (GROUP = 2 or 4)
         const Split2 S = split2(mj, nj, a.pr, a.pc);
         if (im.kind == 0)
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void batch_block_sums_kernel(const float* __re
     const int img = blockIdx.y;
     if (!active[img]) return;
     const BatchImg im = imgs[img];
-    const int mj = (im.H + b - 1) >> lb, nj = (im.W + b - 1) >> lb;
+    const int mj = side_div(im.H + b - 1, b, lb), nj = side_div(im.W + b - 1, b, lb);
     for (int slot = blockIdx.x; slot < mj * nj * nchunk; slot += gridDim.x) {
         const int blk = slot / nchunk, k = slot - blk * nchunk;
         const int p = blk / nj, q = blk - p * nj;
@@ -212,19 +212,19 @@ __global__ __launch_bounds__(256) void batch_fill_kernel(double* __restrict__ x,
 
 // Coarse level end: u += pending correction of the pixel's block.  Grid: x strides pixels, y = image.
 __global__ __launch_bounds__(256) void batch_apply_kernel(float* __restrict__ u, const BatchImg* __restrict__ imgs,
-                                                          const int* __restrict__ active, int lb,
+                                                          const int* __restrict__ active, int b, int lb,
                                                           const double* __restrict__ cpend,
                                                           const long long* __restrict__ pend_off)
 {
     const int img = blockIdx.y;
     if (!active[img]) return;
     const BatchImg im = imgs[img];
-    const int nj = (im.W + (1 << lb) - 1) >> lb;
+    const int nj = side_div(im.W + b - 1, b, lb);
     const size_t n = (size_t)im.H * im.W;
     const double* cp = cpend + pend_off[img];
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(t / im.W), j = (int)(t - (size_t)i * im.W);
-        const double c = cp[(size_t)(i >> lb) * nj + (j >> lb)];
+        const double c = cp[(size_t)side_div(i, b, lb) * nj + side_div(j, b, lb)];
         if (c != 0.0) u[im.off + t] = (float)((double)u[im.off + t] + c);
     }
 }
@@ -331,6 +331,7 @@ using mgc::BatchImg;
 struct mg_curv_batch {
     int n = 0;
     int M = 16, G = 32;
+    int sched = 0;                            // block_schedule, equal across the batch
     int Jmax = 0;
     hipStream_t user_stream = nullptr;
     hipStream_t gstream = nullptr;            // own stream for graph capture and replay
@@ -390,6 +391,23 @@ mg_status bhip(mg_curv_batch* b, hipError_t e, const char* what)
     return bfail(b, MG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+int side_of(const mg_curv_batch* b, int level) { return mgc::block_side(level, b->sched); }
+
+// log2(bs) for a power of two, -1 otherwise
+int lbits(int bs)
+{
+    int l = 0;
+    while ((1 << l) < bs) ++l;
+    return (1 << l) == bs ? l : -1;
+}
+
+// lane-group shapes of a level: those of the power-of-two side that holds its ring
+std::vector<mgc::BlockCfg> candidates_of(const mg_curv_batch* b, int level)
+{
+    const int bs = side_of(b, level);
+    return mgc::block_candidates(bs == 2 ? 2 : mgc::shape_side(bs));
+}
+
 int levels_for(int H, int W)
 {
     int m = H > W ? H : W, J = 0;
@@ -436,10 +454,10 @@ mg_status batch_sweep(mg_curv_batch* b, hipStream_t s, float* u, const float* f,
 {
     hipError_t e;
     if (level == 1) return bfail(b, MG_E_INVALID, "the pixel level runs all colours together");
-    const int bs = 1 << (level - 1);
+    const int bs = side_of(b, level);
     const int li = level - 2;
     const int total = b->blk_total[li * 4 + colour];
-    mgc::BatchLevelArgs a{bs, level - 1, colour >> 1, colour & 1, b->partials, b->d_part_off[li], b->nchunk[li],
+    mgc::BatchLevelArgs a{bs, lbits(bs), colour >> 1, colour & 1, b->partials, b->d_part_off[li], b->nchunk[li],
                           b->cpend, b->d_pend_off[li]};
     const mgc::BlockCfg cfg = b->cfg[li];
     const int grid = cfg.group > 64 ? std::min(total, 2048) : b->grid[level - 1];
@@ -451,14 +469,14 @@ mg_status batch_sweep(mg_curv_batch* b, hipStream_t s, float* u, const float* f,
 
 mg_status batch_level_begin(mg_curv_batch* b, hipStream_t s, const float* u, const float* f, int level)
 {
-    const int bs = 1 << (level - 1), li = level - 2;
+    const int bs = side_of(b, level), li = level - 2;
     int maxslots = 1;
     for (int i = 0; i < b->n; ++i) {
         const int mj = (b->h_imgs[i].H + bs - 1) / bs, nj = (b->h_imgs[i].W + bs - 1) / bs;
         maxslots = std::max(maxslots, mj * nj * b->nchunk[li]);
     }
     hipLaunchKernelGGL(mgc::batch_block_sums_kernel, dim3(std::min(maxslots, 1024), b->n), dim3(256), 0, s, u, f,
-                       b->d_imgs, b->d_active, bs, level - 1, b->nchunk[li], b->rows_per[li], b->partials,
+                       b->d_imgs, b->d_active, bs, lbits(bs), b->nchunk[li], b->rows_per[li], b->partials,
                        b->d_part_off[li]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bhip(b, e, "batched block sums");
@@ -475,8 +493,9 @@ mg_status batch_level_begin(mg_curv_batch* b, hipStream_t s, const float* u, con
 
 mg_status batch_level_end(mg_curv_batch* b, hipStream_t s, float* u, int level)
 {
-    hipLaunchKernelGGL(mgc::batch_apply_kernel, dim3(64, b->n), dim3(256), 0, s, u, b->d_imgs, b->d_active, level - 1,
-                       b->cpend, b->d_pend_off[level - 2]);
+    const int bs = side_of(b, level);
+    hipLaunchKernelGGL(mgc::batch_apply_kernel, dim3(64, b->n), dim3(256), 0, s, u, b->d_imgs, b->d_active, bs,
+                       lbits(bs), b->cpend, b->d_pend_off[level - 2]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bhip(b, e, "batched apply");
     return MG_OK;
@@ -504,7 +523,7 @@ mg_status batch_level(mg_curv_batch* b, hipStream_t s, float* u, const float* f,
         }
         return MG_OK;
     }
-    const bool lazy = mgc::level_is_lazy(1 << (level - 1));
+    const bool lazy = mgc::level_is_lazy(side_of(b, level));
     mg_status st;
     if (lazy && (st = batch_level_begin(b, s, u, f, level)) != MG_OK) return st;
     for (int colour = 0; colour < 4; ++colour)
@@ -572,7 +591,10 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
         if (p.state_dtype != MG_F32) return bfail(nullptr, MG_E_DTYPE, "batched images use float32 state");
         if (p.fine_colours != 4) return bfail(nullptr, MG_E_INVALID, "batched images use four fine colours");
         if (p.cycle != 0) return bfail(nullptr, MG_E_INVALID, "batched images use the half V-cycle");
-        if (p.block_schedule != 0) return bfail(nullptr, MG_E_INVALID, "batched images use power-of-two blocks");
+        if (p.block_schedule != 0 && p.block_schedule != 1)
+            return bfail(nullptr, MG_E_INVALID, "image %d: block_schedule must be 0 or 1", i);
+        if (p.block_schedule != p0.block_schedule)
+            return bfail(nullptr, MG_E_INVALID, "block_schedule must be equal across the batch");
         if (p.samples != p0.samples || p.bisections != p0.bisections)
             return bfail(nullptr, MG_E_INVALID, "samples and bisections must be equal across the batch");
         if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return bfail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");
@@ -587,6 +609,7 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
     b->n = n;
     b->M = p0.samples;
     b->G = p0.bisections;
+    b->sched = p0.block_schedule;
     b->user_stream = (hipStream_t)hip_stream;
     b->P.assign(params, params + n);
     long long off = 0;
@@ -627,7 +650,7 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
     // block levels
     size_t max_part = 1, max_pend = 1;
     for (int level = 2; level <= b->Jmax; ++level) {
-        const int bs = 1 << (level - 1);
+        const int bs = side_of(b, level);
         for (int colour = 0; colour < 4; ++colour) {
             std::vector<int> c(1, 0);
             for (int k = 0; k < n; ++k) {
@@ -664,7 +687,7 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
         ok = ok && upload(b, &dpo, po) && upload(b, &dpe, pe);
         b->d_part_off.push_back(dpo);
         b->d_pend_off.push_back(dpe);
-        b->cfg.push_back(mgc::block_candidates(bs)[0]);
+        b->cfg.push_back(candidates_of(b, level)[0]);
     }
     for (int level = 1; level <= b->Jmax; ++level) b->grid.push_back(default_grid(level));
     ok = ok && dalloc(b, &b->partials, max_part) && dalloc(b, &b->cpend, max_pend);
@@ -705,7 +728,7 @@ mg_status mg_curv_batch_sweep(mg_curv_batch* b, void* u, const void* f, int32_t 
     if (st != MG_OK) return st;
     if (level < 2 || level > b->Jmax) return bfail(b, MG_E_INVALID, "level must be in [2, %d] (use mg_curv_batch_level for 1)", b->Jmax);
     if (colour < 0 || colour > 3) return bfail(b, MG_E_INVALID, "colour must be in [0, 4)");
-    const bool lazy = mgc::level_is_lazy(1 << (level - 1));
+    const bool lazy = mgc::level_is_lazy(side_of(b, level));
     if (lazy && (st = batch_level_begin(b, b->user_stream, (const float*)u, (const float*)f, level)) != MG_OK) return st;
     if ((st = batch_sweep(b, b->user_stream, (float*)u, (const float*)f, level, colour)) != MG_OK) return st;
     if (lazy && (st = batch_level_end(b, b->user_stream, (float*)u, level)) != MG_OK) return st;
@@ -864,11 +887,11 @@ mg_status mg_curv_batch_tune(mg_curv_batch* b, void* u, const void* f, int32_t r
         b->grid[0] = pick;
     }
     for (int level = 2; level <= b->Jmax; ++level) {
-        const int bs = 1 << (level - 1), li = level - 2;
+        const int li = level - 2;
         float best = 1e30f;
         mgc::BlockCfg pick = b->cfg[li];
         int gpick = b->grid[level - 1];
-        for (const mgc::BlockCfg& c : mgc::block_candidates(bs)) {
+        for (const mgc::BlockCfg& c : candidates_of(b, level)) {
             for (int g : grids) {
                 if (c.group > 64 && g != grids[0]) continue;  // one workgroup per item: grid is fixed
                 b->cfg[li] = c;
@@ -909,7 +932,7 @@ mg_status mg_curv_batch_set_config(mg_curv_batch* b, int32_t level, int32_t grou
     if (grid < 1 || grid > 65536) return bfail(b, MG_E_INVALID, "grid must be in [1, 65536]");
     if (level >= 2) {
         bool found = false;
-        for (const mgc::BlockCfg& c : mgc::block_candidates(1 << (level - 1)))
+        for (const mgc::BlockCfg& c : candidates_of(b, level))
             if (c.group == group && c.rpl == records) found = true;
         if (!found) return bfail(b, MG_E_INVALID, "no compiled lane-group shape (%d, %d) for level %d", group, records, level);
         b->cfg[level - 2] = mgc::BlockCfg{group, records};

@@ -77,10 +77,6 @@ __global__ __launch_bounds__(GROUP > 64 ? GROUP : 256) void sweep_blocks_kernel(
     }
 }
 
-// Block index of pixel coordinate i for block side b (lb = log2(b), or -1 when b
-// is not a power of two).
-__device__ __forceinline__ int side_div(int i, int b, int lb) { return lb >= 0 ? i >> lb : i / b; }
-
 // b = 2 (nested schedule): QL lanes per block; blocks off the image border take the
 // mirrored constant-slope form, the border blocks (numbered first) the general records.
 template <typename T, int KIND, int QL>

@@ -341,9 +341,7 @@ __device__ __forceinline__ void solve_ring_cell(const T* __restrict__ uin, T* __
 //   left edge (0, -1): the same with x and y exchanged;
 //   inside (0, 0): u_x, u_y move (+c/2), u_xx, u_yy (-c), u_xy (+c/4): the
 //     general expansion in powers of c with these slopes.
-// Lane 0 takes the top two quadrants, lane 1 the bottom two (rows read in
-// reverse); each lane reads a 4 x 6 tap window once and mirrors columns for its
-// right quadrant in registers.
+// The lanes of a block split the quadrants (see solve_block2_interior).
 // ---------------------------------------------------------------------------
 template <int KIND>
 struct QuadRing {
@@ -533,6 +531,10 @@ __device__ __forceinline__ void solve_block2_interior(T* __restrict__ u, const T
         if constexpr (NQ == 2) u[iy + 1] = (T)(win[2][3] + cval);
     }
 }
+
+// Block index of pixel coordinate i for block side b (lb = log2(b), or -1 when b
+// is not a power of two).
+__host__ __device__ __forceinline__ int side_div(int i, int b, int lb) { return lb >= 0 ? i >> lb : i / b; }
 
 // ---------------------------------------------------------------------------
 // Ring candidates of block rows [r0, r1) x cols [c0, c1) of an H x W image: the

@@ -529,16 +529,18 @@ class BatchSolver:
     """Many images of independent sizes, alphas and curvature kinds in packed float32 buffers.
 
     ``specs`` is a list of dicts with keys height, width, alpha, kind (0 mean, 1 Gaussian) and
-    optionally levels.  Use :meth:`pack` / :meth:`unpack` to move between the packed device
-    buffer and per-image 2-D views."""
+    optionally levels.  ``block_schedule`` (0: sides 2^(j-1), 1: 2^j - 1) applies to every image.
+    Use :meth:`pack` / :meth:`unpack` to move between the packed device buffer and per-image 2-D
+    views."""
 
-    def __init__(self, specs, samples: int = 16, bisections: int = 32, stream=None):
+    def __init__(self, specs, samples: int = 16, bisections: int = 32, stream=None, block_schedule: int = 0):
         n = len(specs)
         arr = (MgCurvParams * n)()
         for i, sp in enumerate(specs):
             p = default_params(int(sp["height"]), int(sp["width"]), alpha=float(sp["alpha"]),
                                curvature=int(sp.get("kind", 0)), levels=int(sp.get("levels", 0)),
-                               state_dtype=MG_F32, fine_colours=4, samples=samples, bisections=bisections)
+                               state_dtype=MG_F32, fine_colours=4, samples=samples, bisections=bisections,
+                               block_schedule=int(block_schedule))
             arr[i] = p
         self.n = n
         self.specs = [dict(sp) for sp in specs]

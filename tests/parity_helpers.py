@@ -38,3 +38,37 @@ def _check_sweep_against_oracle(o, f, before, after, level, colour, fp64=True):
             n_equal += 1
         worst = max(worst, dc)
     return worst, n_equal
+
+
+def _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, levels, schedule=0, threads=8):
+    """Every image of a batch against the float-state oracle, sweep by sweep from the batch's own state."""
+    oracles = [orc.Oracle(sp["height"], sp["width"], sp["alpha"], sp["kind"], round_f32=True, threads=threads,
+                          schedule=schedule) for sp in bs.specs]
+    f64 = [f.astype(np.float64) for f in fs]
+    for level in levels:
+        if level == 1:
+            # the pixel level runs all four colours in one call; check colour by colour through
+            # the oracle's Jacobi semantics by composing its four sweeps
+            before = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            bs.level(ud, fd, 1)
+            after = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            for k, o in enumerate(oracles):
+                if level > o.levels:
+                    continue
+                x = before[k].copy()
+                for colour in range(4):
+                    o.sweep(x, f64[k], 1, colour)
+                # composed over four colours; an FP64 rounding tie may move one float by an ulp
+                diff = np.abs(x - after[k])
+                assert diff.max() <= 1e-5 and np.count_nonzero(diff) <= max(1, diff.size // 1000), k
+            continue
+        for colour in range(4):
+            before = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            bs.sweep(ud, fd, level, colour)
+            after = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
+            for k, o in enumerate(oracles):
+                if level > o.levels:
+                    assert np.array_equal(before[k], after[k])
+                    continue
+                _, n_equal = _check_sweep_against_oracle(o, f64[k], before[k], after[k], level, colour, fp64=False)
+                assert n_equal <= 1, (k, level, colour)

@@ -116,7 +116,7 @@ def _batch_params(lib, shapes, **over):
 
 @pytest.mark.parametrize("over,status", [
     ({"state_dtype": 1}, -3), ({"fine_colours": 9}, -1), ({"height": 1}, -2), ({"alpha": -1.0}, -1),
-    ({"curvature": 5}, -1), ({"block_schedule": 1}, -1),
+    ({"curvature": 5}, -1), ({"block_schedule": 2}, -1),
 ])
 def test_batch_invalid_params(lib, over, status):
     lib.mg_curv_batch_init.restype = C.c_int
@@ -136,6 +136,11 @@ def test_batch_mismatched_search_constants_and_empty(lib):
     arr[1].samples = 8
     b = C.c_void_p()
     assert lib.mg_curv_batch_init(arr, 2, None, C.byref(b)) == -1
+    lib.mg_curv_batch_last_error.restype = C.c_char_p
+    mixed = _batch_params(lib, [(32, 40), (64, 64)])
+    mixed[1].block_schedule = 1
+    assert lib.mg_curv_batch_init(mixed, 2, None, C.byref(b)) == -1
+    assert b"block_schedule" in lib.mg_curv_batch_last_error(None)
     assert lib.mg_curv_batch_init(arr, 0, None, C.byref(b)) == -1
     assert lib.mg_curv_batch_init(None, 2, None, C.byref(b)) == -1
 

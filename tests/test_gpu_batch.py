@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from synth import batch_specs, noisy_image
-from tests.parity_helpers import _check_sweep_against_oracle
+from tests.parity_helpers import _check_batch_sweeps_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -64,39 +64,6 @@ def test_batch_matches_single_images_bitwise(mg):
         assert torch.equal(outs[k], u1), k
         e1 = s.energy(u1, f1)
         assert abs(e1 - e_batch[k]) <= 2.2e-16 * h * w * abs(e1) + 1e-300, (k, e1, e_batch[k])
-
-
-def _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, levels):
-    oracles = [orc.Oracle(sp["height"], sp["width"], sp["alpha"], sp["kind"], round_f32=True, threads=THREADS)
-               for sp in bs.specs]
-    f64 = [f.astype(np.float64) for f in fs]
-    for level in levels:
-        if level == 1:
-            # the pixel level runs all four colours in one call; check colour by colour through
-            # the oracle's Jacobi semantics by composing its four sweeps
-            before = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
-            bs.level(ud, fd, 1)
-            after = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
-            for k, o in enumerate(oracles):
-                if level > o.levels:
-                    continue
-                x = before[k].copy()
-                for colour in range(4):
-                    o.sweep(x, f64[k], 1, colour)
-                # composed over four colours; an FP64 rounding tie may move one float by an ulp
-                diff = np.abs(x - after[k])
-                assert diff.max() <= 1e-5 and np.count_nonzero(diff) <= max(1, diff.size // 1000), k
-            continue
-        for colour in range(4):
-            before = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
-            bs.sweep(ud, fd, level, colour)
-            after = [v.cpu().numpy().astype(np.float64) for v in bs.unpack(ud)]
-            for k, o in enumerate(oracles):
-                if level > o.levels:
-                    assert np.array_equal(before[k], after[k])
-                    continue
-                _, n_equal = _check_sweep_against_oracle(o, f64[k], before[k], after[k], level, colour, fp64=False)
-                assert n_equal <= 1, (k, level, colour)
 
 
 def test_batch_sweeps_match_oracle(mg, orc):

@@ -184,3 +184,49 @@ def test_sampled_parity_1024(mg, orc, kind):
             r0, r1, c0, c1 = o.block_bounds(level, p, q)
             untouched[r0:r1, c0:c1] = False
         assert np.array_equal(after[untouched], before[untouched]), level
+
+
+BATCH = [  # (H, W, alpha, kind): ragged sizes, both kinds, levels up to side 255
+    (40, 56, 20.0, 0), (64, 64, 10.0, 1), (33, 47, 40.0, 0), (130, 96, 20.0, 1),
+    (2, 3, 20.0, 0), (200, 150, 10.0, 0), (300, 260, 20.0, 1),
+]
+
+
+def _batch_images(shapes, seed0=700):
+    return [noisy_image(h, w, seed0 + k, 0.05 + 0.01 * k, dtype=np.float32)[0] for k, (h, w, _, _) in enumerate(shapes)]
+
+
+def test_batch_matches_single_images_bitwise(mg):
+    """The batched path on the paper's schedule (default shapes, which are the single-image ones)
+    reproduces single-image runs bit for bit over three V-cycles."""
+    _case("schedule batch vs single images")
+    fs = _batch_images(BATCH)
+    bs = mg.BatchSolver([dict(height=h, width=w, alpha=a, kind=k) for h, w, a, k in BATCH], block_schedule=PAPER)
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    for _ in range(3):
+        bs.vcycle(ud, fd)
+    outs = bs.unpack(ud)
+    for k, (h, w, a, kind) in enumerate(BATCH):
+        s = mg.Solver(h, w, alpha=a, kind=kind, dtype=torch.float32, block_schedule=PAPER)
+        f1 = torch.tensor(fs[k], device="cuda")
+        u1 = f1.clone()
+        for _ in range(3):
+            s.vcycle(u1, f1)
+        assert torch.equal(outs[k], u1), k
+
+
+def test_batch_sweeps_match_oracle(mg, orc):
+    """Every image of a paper-schedule batch against the oracle with the same schedule, sweep by
+    sweep at every level (side 1 .. 255), after one V-cycle and after autotuning."""
+    from tests.parity_helpers import _check_batch_sweeps_against_oracle
+    _case("schedule batch sweeps vs oracle")
+    fs = _batch_images(BATCH)
+    bs = mg.BatchSolver([dict(height=h, width=w, alpha=a, kind=k) for h, w, a, k in BATCH], block_schedule=PAPER)
+    fd = bs.pack(fs)
+    ud = fd.clone()
+    bs.vcycle(ud, fd)
+    _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, range(1, bs.levels + 1), schedule=PAPER)
+    bs.tune(ud, fd, repeats=1)
+    print("tuned:", [bs.config(l) for l in range(1, bs.levels + 1)])
+    _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, range(2, bs.levels + 1), schedule=PAPER)
