@@ -230,3 +230,40 @@ def test_batch_sweeps_match_oracle(mg, orc):
     bs.tune(ud, fd, repeats=1)
     print("tuned:", [bs.config(l) for l in range(1, bs.levels + 1)])
     _check_batch_sweeps_against_oracle(mg, orc, bs, fs, ud, fd, range(2, bs.levels + 1), schedule=PAPER)
+
+
+def test_sampled_parity_4096_streamed(mg, orc):
+    """4096 x 4096, J = 12, float state, mean curvature: sides 1023, 2047 and 4095 stream their
+    rings from the record scratch (sized for sides that are not powers of two); sampled blocks
+    of one colour per level against the oracle's local solve on the same state, and every pixel
+    outside the colour's blocks unchanged."""
+    h = w = 4096
+    f, _ = _f_and_u(h, w, 3, 0.1, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=0, dtype=torch.float32, block_schedule=PAPER)
+    o = orc.Oracle(h, w, 20.0, 0, round_f32=True, schedule=PAPER, threads=THREADS)
+    assert s.levels == o.levels == 12
+    fd = dev(f, torch.float32)
+    ug = dev(f, torch.float32)
+    s.vcycle(ug, fd)
+    rng = np.random.default_rng(5)
+    for level in (2, 10, 11, 12):
+        colour = int(rng.integers(0, 4))
+        _case(f"schedule sampled 4096 level={level} colour={colour}")
+        before = host(ug)
+        s.sweep(ug, fd, level, colour)
+        after = host(ug)
+        m, n = o.grid(level)
+        cand = [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
+        pick = rng.choice(len(cand), size=min(4, len(cand)), replace=False)
+        for k in pick:
+            p, q = cand[int(k)]
+            r0, r1, c0, c1 = o.block_bounds(level, p, q)
+            info = o.local_solve(before, f, (r0, r1, c0, c1))
+            expect = (before[r0:r1, c0:c1] + info.c).astype(np.float32).astype(np.float64)
+            err = np.max(np.abs(after[r0:r1, c0:c1] - expect))
+            assert err <= 2.5e-7, (level, p, q, err, info.c)
+        untouched = np.ones((h, w), dtype=bool)
+        for p, q in cand:
+            r0, r1, c0, c1 = o.block_bounds(level, p, q)
+            untouched[r0:r1, c0:c1] = False
+        assert np.array_equal(after[untouched], before[untouched]), level
