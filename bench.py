@@ -47,9 +47,9 @@ SEED = 0
 FLOPS_VALUE = {0: 103, 1: 97}
 FLOPS_DERIV = {0: 148, 1: 141}
 N_VALUE, N_DERIV = 19, 32
-# The survey's per-unit figure for the same work: about 40 (mean) or 30 (Gaussian) flops per
-# ring-pixel evaluation with general affine records, 9 ring pixels, 51 evaluations per pixel.
-FLOPS_SURVEY_PIXEL = {0: 9 * 51 * 40, 1: 9 * 51 * 30}
+# The same work counted with general affine ring records instead: about 40 (mean) or 30
+# (Gaussian) flops per ring-pixel evaluation, 9 ring pixels, 51 evaluations per pixel.
+FLOPS_GENERAL_PIXEL = {0: 9 * 51 * 40, 1: 9 * 51 * 30}
 FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
 
 
@@ -373,7 +373,7 @@ def main():
     avg_ms = ev0.elapsed_time(ev1) / launches
     pixels_per_launch = (H // 2) * (W // 2)
     flops_launch = pixels_per_launch * (N_VALUE * FLOPS_VALUE[args.kind] + N_DERIV * FLOPS_DERIV[args.kind])
-    flops_survey = pixels_per_launch * FLOPS_SURVEY_PIXEL[args.kind]
+    flops_general = pixels_per_launch * FLOPS_GENERAL_PIXEL[args.kind]
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
 
     # per-level times (one V-cycle's share), for the report
@@ -428,7 +428,7 @@ def main():
                      "kernel": "sweep_pixels_kernel (b = 1)", "avg_launch_ms": round(avg_ms, 5),
                      "flops_per_launch": flops_launch,
                      "flops_counted_as": "executed formula (FP64, interior-pixel form)",
-                     "survey_per_unit_tflops": round(flops_survey / (avg_ms * 1e-3) / 1e12, 3),
+                     "general_records_tflops": round(flops_general / (avg_ms * 1e-3) / 1e12, 3),
                      "note": "one launch = one colour of the pixel level (outer ring of cells on 16-lane "
                              "groups, interior cells one thread each), timed with HIP events on the library stream"},
         "level_ms": level_ms,

@@ -5,8 +5,8 @@ batched multigrid solver itself returns for f (mean curvature, alpha 20, stop at
 energy change of 1e-6).  At solve time u0 = f + g(f) replaces u0 = f, and the multigrid
 refines u0 until its energy reaches the plain solve's final energy F_plain (1 + 1e-6); an image
 whose warm-started refinement does not get there within the V-cycle budget falls back to the
-plain solve from u0 = f, whose time is then counted too.  The plain solve remains the judge of
-the final energy.
+plain solve from u0 = f, whose time is then counted too.  The plain solve's energy remains the
+reference the final energy is held to.
 
     python -m paper_2204_07921_amd.warmstart train --pairs 20000 --size 256 --steps 3000 --out W.npz
     python -m paper_2204_07921_amd.warmstart eval --weights W.npz --n 64 --size 1024
