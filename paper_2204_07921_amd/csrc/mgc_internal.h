@@ -28,7 +28,8 @@ struct CoarseScratch {
 // (schedule 1, the patch side of Section 2.2).  Level 1 is the pixel level in both.
 inline int block_side(int level, int schedule)
 {
-    return schedule == 1 ? (1 << level) - 1 : 1 << (level - 1);
+    // unsigned: level 31 (2^31 - 1) is in range for a 2^29-pixel-wide image
+    return schedule == 1 ? (int)((1u << level) - 1u) : (int)(1u << (level - 1));
 }
 // Smallest power of two >= b: the lane-group shape of a level is that of this side
 // (a 2^j - 1 ring has 8 fewer pixels than the 2^j one, so the same slots hold it).

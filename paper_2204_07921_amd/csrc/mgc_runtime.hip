@@ -223,6 +223,8 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
         return fail(nullptr, MG_E_INVALID, "block_schedule must be 0 (2^(j-1)) or 1 (2^j - 1)");
     const int Jmax = auto_levels(p.height, p.width) + 1;
     if (p.levels < 0 || p.levels > Jmax) return fail(nullptr, MG_E_INVALID, "levels must be in [0, %d]", Jmax);
+    if (p.block_schedule == 1 && p.levels > 30)   // side 2^31 - 1 would overflow the block arithmetic
+        return fail(nullptr, MG_E_INVALID, "levels must be <= 30 with block_schedule 1");
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);

@@ -145,6 +145,23 @@ def test_batch_mismatched_search_constants_and_empty(lib):
     assert lib.mg_curv_batch_init(None, 2, None, C.byref(b)) == -1
 
 
+def test_paper_schedule_level_limit(lib):
+    """Side 2^31 - 1 does not fit the block arithmetic: levels = 31 on the 2^j - 1 schedule is
+    rejected before any device work, for single images and batches (a 2^29 + 1 by 2 image allows
+    31 levels on the power-of-two schedule)."""
+    p = Params()
+    lib.mg_curv_default_params(C.byref(p), (1 << 29) + 1, 2)
+    p.levels, p.block_schedule = 31, 1
+    ctx = C.c_void_p(1234)
+    assert lib.mg_curv_init(C.byref(p), None, C.byref(ctx)) == -1
+    assert b"30" in lib.mg_curv_last_error(None)
+    lib.mg_curv_batch_init.restype = C.c_int
+    lib.mg_curv_batch_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    arr = (Params * 1)(p)
+    b = C.c_void_p()
+    assert lib.mg_curv_batch_init(arr, 1, None, C.byref(b)) == -1
+
+
 def test_batch_no_device(lib):
     import torch
     if torch.cuda.is_available():
