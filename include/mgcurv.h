@@ -70,8 +70,8 @@ typedef struct {
     int32_t width;         /* W >= 2 */
     double alpha;          /* data weight of eq. MCM / GCM, finite and > 0 */
     int32_t curvature;     /* mg_curv_kind */
-    int32_t levels;        /* J >= 1, at most ceil(log2(max(H, W))) + 1 (and 30 with
-                              block_schedule 1); 0 selects ceil(log2(max(H, W))) */
+    int32_t levels;        /* J >= 1, at most ceil(log2(max(H, W))) + 1, and the block side
+                              at level J at most 2^26; 0 selects ceil(log2(max(H, W))) */
     int32_t state_dtype;   /* mg_dtype of u and f; the local minimisation always runs in FP64 */
     int32_t fine_colours;  /* colours at the pixel level (b = 1): 4 (Section 2.3) or 9
                               (3 x 3 pattern; pixels of one colour then share no ring pixel) */

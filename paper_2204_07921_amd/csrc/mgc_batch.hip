@@ -600,8 +600,10 @@ mg_status mg_curv_batch_init(const mg_curv_params* params, int32_t n, void* hip_
         if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return bfail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");
         if (p.bisections < 0 || p.bisections > 64) return bfail(nullptr, MG_E_INVALID, "bisections must be in [0, 64]");
         const int Ja = levels_for(p.height, p.width);
-        if (p.levels < 0 || p.levels > Ja + 1 || (p.block_schedule == 1 && p.levels > 30))
-            return bfail(nullptr, MG_E_INVALID, "image %d: levels out of range", i);
+        if (p.levels < 0 || p.levels > Ja + 1) return bfail(nullptr, MG_E_INVALID, "image %d: levels out of range", i);
+        const int Ji = p.levels > 0 ? p.levels : Ja;
+        if (Ji > 27 || mgc::block_side(Ji, p.block_schedule) > (1 << 26))
+            return bfail(nullptr, MG_E_INVALID, "image %d: the block side at level %d exceeds 2^26 pixels", i, Ji);
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return bfail(nullptr, MG_E_DEVICE, "no HIP device available");

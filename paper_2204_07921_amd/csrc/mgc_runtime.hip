@@ -219,12 +219,15 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     if (p.samples < 2 || p.samples > 256 || (p.samples & 1)) return fail(nullptr, MG_E_INVALID, "samples must be even and in [2, 256]");
     if (p.bisections < 0 || p.bisections > 64) return fail(nullptr, MG_E_INVALID, "bisections must be in [0, 64]");
     if (p.cycle != 0 && p.cycle != 1) return fail(nullptr, MG_E_INVALID, "cycle must be 0 (half) or 1 (full)");
-    if (p.block_schedule != 0 && p.block_schedule != 1)
-        return fail(nullptr, MG_E_INVALID, "block_schedule must be 0 (2^(j-1)) or 1 (2^j - 1)");
     const int Jmax = auto_levels(p.height, p.width) + 1;
     if (p.levels < 0 || p.levels > Jmax) return fail(nullptr, MG_E_INVALID, "levels must be in [0, %d]", Jmax);
-    if (p.block_schedule == 1 && p.levels > 30)   // side 2^31 - 1 would overflow the block arithmetic
-        return fail(nullptr, MG_E_INVALID, "levels must be <= 30 with block_schedule 1");
+    if (p.block_schedule != 0 && p.block_schedule != 1)
+        return fail(nullptr, MG_E_INVALID, "block_schedule must be 0 (2^(j-1)) or 1 (2^j - 1)");
+    {   // ring counts (8b) and record strides stay in int range
+        const int J = p.levels > 0 ? p.levels : auto_levels(p.height, p.width);
+        if (J > 27 || mgc::block_side(J, p.block_schedule) > (1 << 26))
+            return fail(nullptr, MG_E_INVALID, "the block side at level %d exceeds 2^26 pixels; use fewer levels", J);
+    }
 
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);

@@ -145,21 +145,28 @@ def test_batch_mismatched_search_constants_and_empty(lib):
     assert lib.mg_curv_batch_init(None, 2, None, C.byref(b)) == -1
 
 
-def test_paper_schedule_level_limit(lib):
-    """Side 2^31 - 1 does not fit the block arithmetic: levels = 31 on the 2^j - 1 schedule is
-    rejected before any device work, for single images and batches (a 2^29 + 1 by 2 image allows
-    31 levels on the power-of-two schedule)."""
+@pytest.mark.parametrize("levels,schedule,status", [
+    (0, 0, -1), (31, 1, -1), (28, 0, -1), (27, 1, -1), (27, 0, -5), (26, 1, -5)])
+def test_block_side_limit(lib, levels, schedule, status):
+    """Ring counts (8b) must stay in int range: a level whose block side exceeds 2^26 is rejected
+    before any device work, for single images and batches.  A 2^29 + 1 by 2 image would default
+    to J = 30 (side 2^29); J = 27 is the largest with nested blocks (2^26) and J = 26 with
+    2^j - 1 blocks.  Allowed cases reach the device check (-5 without a GPU)."""
+    import torch
+    if status == -5 and torch.cuda.is_available():
+        pytest.skip("a GPU is present; the allowed cases would allocate a 2^30-pixel image")
     p = Params()
     lib.mg_curv_default_params(C.byref(p), (1 << 29) + 1, 2)
-    p.levels, p.block_schedule = 31, 1
+    p.levels, p.block_schedule = levels, schedule
     ctx = C.c_void_p(1234)
-    assert lib.mg_curv_init(C.byref(p), None, C.byref(ctx)) == -1
-    assert b"30" in lib.mg_curv_last_error(None)
-    lib.mg_curv_batch_init.restype = C.c_int
-    lib.mg_curv_batch_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
-    arr = (Params * 1)(p)
-    b = C.c_void_p()
-    assert lib.mg_curv_batch_init(arr, 1, None, C.byref(b)) == -1
+    assert lib.mg_curv_init(C.byref(p), None, C.byref(ctx)) == status
+    if status == -1:
+        assert b"2^26" in lib.mg_curv_last_error(None)
+        lib.mg_curv_batch_init.restype = C.c_int
+        lib.mg_curv_batch_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+        arr = (Params * 1)(p)
+        b = C.c_void_p()
+        assert lib.mg_curv_batch_init(arr, 1, None, C.byref(b)) == -1
 
 
 def test_batch_no_device(lib):
