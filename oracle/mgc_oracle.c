@@ -41,7 +41,9 @@
  *     sample c_i = f* + rho (2 i - M) / M, i = 0..M; i* = first arg min V(c_i),
  *     bisection on the sign of V'(c) in [c_{i*-1}, c_{i*+1}] for G steps,
  *     choose the bisection point unless the best sample is lower by more than
- *     eta = 1e-12 (1 + V(0)), accept it when F decreases by more than -eta.
+ *     eta = 1e-12 (1 + V(0)), and accept the chosen point only when it lowers
+ *     the local energy strictly (Delta < 0): c = 0 is always a candidate of the
+ *     arg min, so a block update never raises F.
  *
  * The ring of a block B is the set of pixels p in the image whose clamped 3x3
  * tap set holds at least one tap in B and one tap outside B; every other
@@ -327,7 +329,7 @@ double orc_local_solve(const orc_params *P, const double *u, const double *f,
     }
     double Kt = orc_ring_K(kind, u, H, W, r0, r1, c0, c1, c_tilde);
     double delta = (Kt - K0) + 0.5 * as * c_tilde * (c_tilde - 2.0 * fs);
-    int accepted = delta < eta;
+    int accepted = delta < 0.0;
     double c = accepted ? c_tilde : 0.0;
     if (info) {
         info->s = s; info->fs = fs; info->K0 = K0; info->Kf = Kf; info->rho = rho;

@@ -38,7 +38,16 @@ MUTANTS = [
     ("derivative_no_sign", "double s = (k > 0.0) - (k < 0.0);", "double s = 1.0;"),
     ("bracket_too_narrow", "const double rho = sqrt(2.0 * Kf / as);", "const double rho = sqrt(0.05 * Kf / as);"),
     ("mean_not_sum", "const double fs = r / s;", "const double fs = r;"),
-    ("no_accept_test", "int accepted = delta < eta;", "int accepted = 1;"),
+    ("no_accept_test", "int accepted = delta < 0.0;", "int accepted = 1;"),
+    ("accept_within_eta", "int accepted = delta < 0.0;", "int accepted = delta < eta;"),
+    ("sweep_in_place", "        cs[t] = orc_local_solve(P, u, f, r0, r1, c0, c1, NULL);\n    }",
+     "        cs[t] = orc_local_solve(P, u, f, r0, r1, c0, c1, NULL);\n"
+     "        for (int i = r0; i < r1; ++i)\n"
+     "            for (int j = c0; j < c1; ++j) u[(size_t)i * W + j] += cs[t];\n"
+     "        cs[t] = 0.0;\n    }"),
+    ("stop_absolute_change", "fabs(e - e_prev) < rel_tol * fabs(e)", "fabs(e - e_prev) < rel_tol"),
+    ("stop_against_first_energy", "        if (rel_tol > 0.0 && (e == e_prev || fabs(e - e_prev) < rel_tol * fabs(e))) break;\n        e_prev = e;",
+     "        if (rel_tol > 0.0 && (e == e_prev || fabs(e - e_prev) < rel_tol * fabs(e))) break;"),
     ("colour_map", "return ncol == 9 ? 3 * (p % 3) + (q % 3) : 2 * (p % 2) + (q % 2);",
      "return ncol == 9 ? 3 * (p % 3) + (q % 3) : 2 * (q % 2) + (p % 2);"),
     ("schedule_side_pow2", "return P->schedule == 1 ? (1 << level) - 1 : 1 << (level - 1);",
