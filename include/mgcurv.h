@@ -19,8 +19,9 @@
  * colour.  The one-dimensional minimisation samples the bracket
  * [f* - rho, f* + rho] (f* = mean of f - u over B, rho = sqrt(2 K(f*) / (alpha |B|)))
  * at `samples` + 1 points, refines the best one by `bisections` bisection
- * steps on the sign of the derivative, and keeps c = 0 unless the local
- * energy does not rise.
+ * steps on the sign of the derivative, and keeps c = 0 unless the result
+ * lowers the local energy by more than the rounding margin 1e-12 (1 + V(0))
+ * of the computed change (V(0) = the block's local energy at c = 0).
  *
  * Conventions for every entry point:
  *   - u and f are DEVICE pointers to contiguous row-major H x W arrays of

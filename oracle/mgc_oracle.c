@@ -42,8 +42,10 @@
  *     bisection on the sign of V'(c) in [c_{i*-1}, c_{i*+1}] for G steps,
  *     choose the bisection point unless the best sample is lower by more than
  *     eta = 1e-12 (1 + V(0)), and accept the chosen point only when it lowers
- *     the local energy strictly (Delta < 0): c = 0 is always a candidate of the
- *     arg min, so a block update never raises F.
+ *     the local energy by more than eta (Delta < -eta): c = 0 is always a
+ *     candidate of the arg min and wins every tie that rounding cannot resolve
+ *     (eta bounds the rounding of the computed Delta, a difference of two ring
+ *     sums), so an applied block update lowers F.
  *
  * The ring of a block B is the set of pixels p in the image whose clamped 3x3
  * tap set holds at least one tap in B and one tap outside B; every other
@@ -329,7 +331,7 @@ double orc_local_solve(const orc_params *P, const double *u, const double *f,
     }
     double Kt = orc_ring_K(kind, u, H, W, r0, r1, c0, c1, c_tilde);
     double delta = (Kt - K0) + 0.5 * as * c_tilde * (c_tilde - 2.0 * fs);
-    int accepted = delta < 0.0;
+    int accepted = delta < -eta;
     double c = accepted ? c_tilde : 0.0;
     if (info) {
         info->s = s; info->fs = fs; info->K0 = K0; info->Kf = Kf; info->rho = rho;

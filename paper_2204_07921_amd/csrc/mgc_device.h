@@ -375,8 +375,9 @@ struct NoSum {
 // c_i = fs + rho (2 i - M) / M, i* = first arg min of V(c_i), G bisection
 // steps on the sign of V' in [c_{i*-1}, c_{i*+1}], the bisection point wins
 // unless the best sample is lower by more than eta = 1e-12 (1 + V(0)), and the
-// result is kept only if it lowers the local energy strictly (c = 0 is always a
-// candidate of the arg min, so no block update raises the energy).
+// result is kept only if it lowers the local energy by more than eta (c = 0 is
+// always a candidate of the arg min and wins the ties rounding cannot resolve,
+// so an applied block update lowers the energy).
 // ---------------------------------------------------------------------------
 template <class KP, class DP, class GS>
 __device__ __forceinline__ double local_solve(KP&& Kpart, DP&& Dpart, const GS& gs, double fs, double as, int M, int G)
@@ -460,7 +461,7 @@ __device__ __forceinline__ double local_solve(KP&& Kpart, DP&& Dpart, const GS& 
         else scan(std::false_type());
     }
     const double delta = (Kt - K0) + 0.5 * as * ct * (ct - 2.0 * fs);
-    return delta < 0.0 ? ct : 0.0;
+    return delta < -eta ? ct : 0.0;
 }
 
 }  // namespace mgc

@@ -13,16 +13,18 @@ Tolerances, derived from the arithmetic:
   * Energy: two summation orders of N non-negative terms differ by at most
     about 2 N eps relative.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
 
 from synth import noisy_image
-from tests.parity_helpers import _blocks_of, _check_sweep_against_oracle
+from tests.parity_helpers import _blocks_of, _check_sweep_against_oracle, assert_untouched, full_grid_check
 
 pytestmark = pytest.mark.gpu
 
-THREADS = 8
+THREADS = min(16, os.cpu_count() or 1)
 
 
 @pytest.fixture(scope="module")
@@ -288,6 +290,7 @@ def _sampled_check(mg, orc, h, w, kind, dtype, levels_to_check, n_samples, warm_
         before = host(ug)
         s.sweep(ug, fd, level, colour)
         after = host(ug)
+        assert_untouched(o, before, after, level, colour)
         m, n = o.grid(level)
         cand = [(p, q) for p in range(m) for q in range(n) if o.colour_of(level, p, q) == colour]
         pick = rng.choice(len(cand), size=min(n_samples, len(cand)), replace=False)
@@ -305,17 +308,90 @@ def _sampled_check(mg, orc, h, w, kind, dtype, levels_to_check, n_samples, warm_
     return worst
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("sigma", [0.05, 0.1])
 @pytest.mark.parametrize("kind", [0, 1])
-def test_sampled_parity_1024_fp32(mg, orc, kind):
-    """1024x1024 in the launch configuration the benchmark times: sampled blocks of one colour
-    at fine, middle and coarsest levels against the oracle's local solve on the same state."""
-    worst = _sampled_check(mg, orc, 1024, 1024, kind, torch.float32, [1, 2, 3, 5, 8, 10], 24, 3)
-    print(f"worst sampled error {worst:.3e}")
+def test_full_grid_parity_1024(mg, orc, kind, sigma, dtype):
+    """1024x1024, J = 10, the benchmark's launch configuration: after 3 V-cycles from u = f, every
+    colour sweep of one more V-cycle (all ten levels) is compared pixel by pixel with the oracle's
+    sweep from the GPU's own state (float state against the oracle's float-state option, bitwise
+    except where the arg-min is ill-conditioned; FP64 state to 1e-10)."""
+    h = w = 1024
+    fp64 = dtype == torch.float64
+    f, _ = _f_and_u(h, w, 0, sigma, dtype)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype)
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=not fp64, threads=THREADS)
+    assert s.levels == o.levels == 10
+    fd = dev(f, dtype)
+    ug = dev(f, dtype)
+    for _ in range(3):
+        s.vcycle(ug, fd)
+    total_blocks = total_equal = 0
+    worst = 0.0
+    for level in range(1, s.levels + 1):
+        for colour in range(4):
+            _case(f"full grid 1024 kind={kind} sigma={sigma} {dtype} level={level} colour={colour}")
+            before = host(ug)
+            s.sweep(ug, fd, level, colour)
+            after = host(ug)
+            n_blocks, n_equal, w_ = full_grid_check(o, f, before, after, level, colour, fp64)
+            # ill-conditioned arg-mins are rare: at most 1 in 1000 blocks of a sweep (and 2 at coarse levels)
+            assert n_equal <= max(2, n_blocks // 1000), (level, colour, n_equal, n_blocks)
+            total_blocks += n_blocks
+            total_equal += n_equal
+            worst = max(worst, w_)
+    print(f"full-grid parity: {total_blocks} blocks, {total_equal} on the equal-minimum criterion, "
+          f"max |u_gpu - u_oracle| elsewhere {worst:.3e}")
+    assert worst <= (1e-10 if fp64 else 0.0)
 
 
-def test_sampled_parity_1024_fp64(mg, orc):
-    worst = _sampled_check(mg, orc, 1024, 1024, 0, torch.float64, [1, 2, 4, 6, 9, 10], 16, 2)
-    print(f"worst sampled error {worst:.3e}")
+@pytest.mark.parametrize("sigma", [0.05, 0.1])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_converged_state_1024_is_stationary_under_oracle(mg, orc, kind, sigma):
+    """The end state of a 1024x1024 solve (float state, stop at a relative energy change below 1e-6):
+    the method is nonconvex and its iteration chaotic at kinks of |kappa|, so the end state is
+    judged by whether it is a stopping point of the oracle's own iteration.  From the GPU's final u,
+    one oracle V-cycle (float-state option) lowers F by less than 1e-6 relative, and by the same
+    amount as the GPU's own next V-cycle from that state.
+
+    Mean curvature at sigma 0.05 does not reach the 1e-6 rule: its energy keeps falling by about
+    1.4e-6 of itself per V-cycle for thousands of V-cycles (0.23 % between V-cycles 400 and 2000).
+    There the end state after 400 V-cycles is checked the same way: the oracle's next V-cycle
+    lowers F by the same amount as the GPU's (both still about 1.4e-6)."""
+    h = w = 1024
+    creeps = (kind, sigma) == (0, 0.05)
+    _case(f"converged 1024 kind={kind} sigma={sigma}")
+    f, _ = _f_and_u(h, w, 0, sigma, torch.float32)
+    s = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=torch.float32)
+    fd = dev(f, torch.float32)
+    ug = dev(f, torch.float32)
+    res = s.solve(ug, fd, rel_tol=1e-6, max_vcycles=400 if creeps else 2000, trace=True)
+    tr = res["trace"]
+    last = abs(tr[-1] - tr[-2]) / tr[-1]
+    u_end = host(ug)
+    e_end = res["energy"]
+    # the GPU's own next V-cycle from the end state
+    un = ug.clone()
+    e_next = s.vcycle(un, fd, want_energy=True)
+    g = (e_end - e_next) / e_end
+    # the oracle's V-cycle from the same state
+    o = orc.Oracle(h, w, 20.0, kind, round_f32=True, threads=THREADS)
+    e0 = o.energy(u_end, f)
+    x = u_end.copy()
+    o.vcycle(x, f)
+    e1 = o.energy(x, f)
+    r = (e0 - e1) / e0
+    du_next = float(np.max(np.abs(host(un) - x)))
+    print(f"status {res['status']} after {res['vcycles']} V-cycles, last change {last:.3e}; "
+          f"next V-cycle: GPU {g:.3e}, oracle {r:.3e}; max |u_gpu - u_oracle| after it {du_next:.3e}; "
+          f"energy GPU {e_end:.10f} oracle {e0:.10f}")
+    assert abs(e0 - e_end) <= 2.2e-16 * h * w * e_end
+    if creeps:
+        assert res["status"] == 1 and 0.0 < r < 2e-6
+    else:
+        assert res["status"] == 0
+        assert -1e-12 <= r < 1e-6
+    assert abs(r - g) <= 1e-8
 
 
 @pytest.mark.parametrize("kind", [0, 1])

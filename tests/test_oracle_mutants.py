@@ -38,8 +38,9 @@ MUTANTS = [
     ("derivative_no_sign", "double s = (k > 0.0) - (k < 0.0);", "double s = 1.0;"),
     ("bracket_too_narrow", "const double rho = sqrt(2.0 * Kf / as);", "const double rho = sqrt(0.05 * Kf / as);"),
     ("mean_not_sum", "const double fs = r / s;", "const double fs = r;"),
-    ("no_accept_test", "int accepted = delta < 0.0;", "int accepted = 1;"),
-    ("accept_within_eta", "int accepted = delta < 0.0;", "int accepted = delta < eta;"),
+    ("no_accept_test", "int accepted = delta < -eta;", "int accepted = 1;"),
+    ("accept_within_eta", "int accepted = delta < -eta;", "int accepted = delta < eta;"),
+    ("accept_unresolved_tie", "int accepted = delta < -eta;", "int accepted = delta < 0.0;"),
     ("sweep_in_place", "        cs[t] = orc_local_solve(P, u, f, r0, r1, c0, c1, NULL);\n    }",
      "        cs[t] = orc_local_solve(P, u, f, r0, r1, c0, c1, NULL);\n"
      "        for (int i = r0; i < r1; ++i)\n"
