@@ -144,6 +144,25 @@ mg_status mg_curv_solve_target(mg_curv_ctx *ctx, void *u, const void *f, double 
  * bitwise reproducible for a given size and launch). */
 mg_status mg_curv_energy(mg_curv_ctx *ctx, const void *u, const void *f, double *energy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * of mg_curv_energy without a context.  params gives H, W, alpha, curvature
+ * and state_dtype (the other fields are ignored); u and f are device arrays
+ * as for every entry point, and energy is a DEVICE pointer to one double that
+ * receives F(u) (same kernels and summation order as mg_curv_energy, so the
+ * same value bit for bit).  Enqueued on hip_stream only; the call returns
+ * without waiting.  The partial sums (at most 2048 doubles) live in a
+ * static device array of the library, one per GPU, whose address is looked up
+ * on the first call on each device; the call makes no device allocation.
+ * Calls that overlap in time on one GPU (other streams or threads) share that
+ * array and race.  Errors (before anything is enqueued): MG_E_INVALID /
+ * MG_E_SHAPE / MG_E_DTYPE for bad parameters, null or overlapping pointers;
+ * MG_E_SHAPE for more than 2^31 - 1 pixels; MG_E_DEVICE if no device is
+ * current or a HIP call fails.  mg_curv_last_error(NULL) describes the
+ * failure. */
+mg_status mg_curv_energy_noalloc(const mg_curv_params *params, void *hip_stream, const void *u, const void *f,
+                                 double *energy);
+
 /* One colour sweep of one level (1-based level, colour in [0, 4) or
  * [0, 9) at level 1 with nine fine colours), in place on u.  This is the
  * unit a V-cycle repeats; it is exported so a caller can inspect single

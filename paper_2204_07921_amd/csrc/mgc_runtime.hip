@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -181,6 +182,37 @@ mg_status energy(mg_curv_ctx* ctx, const void* u, const void* f, double* out)
     if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
     *out = *ctx->energy_host;
     return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free energy (mg_curv_energy_noalloc).  Its partial sums live in a
+// file-scope device array of fixed size instead of a context's allocation.
+// In host code `scratch` names a host-side stand-in, not device memory: the
+// array's device address on each GPU is looked up once (hipGetSymbolAddress,
+// with that device current) and only that address is handed to kernels.
+// Every call on one device shares the array; each launch overwrites the
+// partials it reads, so nothing needs clearing, and calls that overlap in time
+// on one device (two streams, two threads) race.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_PARTIALS = 2048;   // = the most energy_partials_count returns
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this device's copy of `scratch` (looked up on first use).
+hipError_t noalloc_scratch(int device, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -436,3 +468,45 @@ const char* mg_curv_last_error(const mg_curv_ctx* ctx)
 }
 
 }  // extern "C"
+
+extern "C" mg_status mg_curv_energy_noalloc(const mg_curv_params* params, void* hip_stream, const void* u,
+                                            const void* f, double* energy_dev)
+{
+    if (!params) return fail(nullptr, MG_E_INVALID, "params must be non-null");
+    const mg_curv_params& p = *params;
+    if (p.height < 2 || p.width < 2) return fail(nullptr, MG_E_SHAPE, "height and width must be >= 2 (got %d x %d)", p.height, p.width);
+    if ((int64_t)p.height * p.width > ((int64_t)1 << 31) - 1)
+        return fail(nullptr, MG_E_SHAPE, "image larger than 2^31 - 1 pixels");
+    if (mgc::energy_partials_count(p.height, p.width) > NOALLOC_PARTIALS)
+        return fail(nullptr, MG_E_SHAPE, "the energy needs more than %d partial sums", NOALLOC_PARTIALS);
+    if (!(p.alpha > 0.0) || !std::isfinite(p.alpha)) return fail(nullptr, MG_E_INVALID, "alpha must be finite and > 0");
+    if (p.curvature != MG_CURV_MEAN && p.curvature != MG_CURV_GAUSS) return fail(nullptr, MG_E_INVALID, "curvature must be 0 (mean) or 1 (Gaussian)");
+    if (p.state_dtype != MG_F32 && p.state_dtype != MG_F64) return fail(nullptr, MG_E_DTYPE, "state_dtype must be MG_F32 or MG_F64");
+    if (!u || !f || !energy_dev) return fail(nullptr, MG_E_INVALID, "u, f and energy must be non-null device pointers");
+    const size_t n = (size_t)p.height * p.width * (p.state_dtype == MG_F64 ? 8 : 4);
+    const char* a = (const char*)u;
+    const char* b = (const char*)f;
+    const char* o = (const char*)energy_dev;
+    if (a < b + n && b < a + n) return fail(nullptr, MG_E_INVALID, "u must not overlap f");
+    if ((o < a + n && a < o + sizeof(double)) || (o < b + n && b < o + sizeof(double)))
+        return fail(nullptr, MG_E_INVALID, "the energy output must not overlap u or f");
+    int device = -1;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return fail(nullptr, MG_E_DEVICE, "no HIP device available: %s", hipGetErrorString(e));
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return fail(nullptr, MG_E_DEVICE, "device index %d out of range", device);
+    double* partials = nullptr;
+    e = noalloc_scratch(device, &partials);
+    if (e != hipSuccess) return fail(nullptr, MG_E_DEVICE, "scratch address lookup: %s", hipGetErrorString(e));
+    mgc::LaunchCtx L;
+    L.stream = (hipStream_t)hip_stream;
+    L.H = p.height;
+    L.W = p.width;
+    L.alpha = p.alpha;
+    L.kind = p.curvature;
+    L.f64 = p.state_dtype == MG_F64;
+    L.M = p.samples;
+    L.G = p.bisections;
+    e = mgc::launch_energy(L, u, f, partials, energy_dev);
+    if (e != hipSuccess) return fail(nullptr, MG_E_DEVICE, "energy launch: %s", hipGetErrorString(e));
+    return MG_OK;
+}

@@ -60,6 +60,8 @@ def _load() -> C.CDLL:
     L.mg_curv_default_params.argtypes = [P, C.c_int32, C.c_int32]
     L.mg_curv_init.restype = C.c_int
     L.mg_curv_init.argtypes = [P, vp, C.POINTER(vp)]
+    L.mg_curv_energy_noalloc.restype = C.c_int
+    L.mg_curv_energy_noalloc.argtypes = [P, vp, cvp, cvp, vp]
     L.mg_curv_vcycle.restype = C.c_int
     L.mg_curv_vcycle.argtypes = [vp, vp, cvp, C.POINTER(C.c_double)]
     L.mg_curv_solve.restype = C.c_int
@@ -264,6 +266,15 @@ def mg_curv_energy(ctx, params, u, f) -> float:
     e = C.c_double()
     _check(lib.mg_curv_energy(ctx, _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"), C.byref(e)), ctx)
     return e.value
+
+
+def mg_curv_energy_noalloc(params, u, f, out, stream=None) -> None:
+    """F(u) into the one-element float64 device tensor `out`, enqueued only (no context, no allocation)."""
+    if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 1 and out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 device tensor with at least one element")
+    _check(lib.mg_curv_energy_noalloc(C.byref(params), C.c_void_p(_stream_handle(stream)),
+                                      _tensor_ptr(u, params, "u"), _tensor_ptr(f, params, "f"),
+                                      C.c_void_p(out.data_ptr())))
 
 
 def mg_curv_sweep(ctx, params, u, f, level: int, colour: int) -> None:

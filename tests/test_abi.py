@@ -280,3 +280,24 @@ def test_recon_params_layout_and_validation(lib):
     lib.mg_recon_destroy(None)
     if not torch.cuda.is_available():
         assert lib.mg_recon_init(C.byref(p), None, C.byref(ctx)) == -5
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("height", 1, -2), ("alpha", 0.0, -1), ("curvature", 3, -1), ("state_dtype", 4, -3),
+])
+def test_energy_noalloc_validates_before_device(lib, field, value, status):
+    lib.mg_curv_energy_noalloc.restype = C.c_int
+    lib.mg_curv_energy_noalloc.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    p = Params()
+    lib.mg_curv_default_params(C.byref(p), 64, 64)
+    setattr(p, field, value)
+    assert lib.mg_curv_energy_noalloc(C.byref(p), None, C.c_void_p(4096), C.c_void_p(1 << 20),
+                                      C.c_void_p(1 << 24)) == status
+    assert lib.mg_curv_last_error(None)
+    assert lib.mg_curv_energy_noalloc(None, None, None, None, None) == -1
+    lib.mg_curv_default_params(C.byref(p), 64, 64)
+    # u overlapping f, and a null output, are rejected before any device call
+    assert lib.mg_curv_energy_noalloc(C.byref(p), None, C.c_void_p(4096), C.c_void_p(4096 + 64),
+                                      C.c_void_p(1 << 24)) == -1
+    assert lib.mg_curv_energy_noalloc(C.byref(p), None, C.c_void_p(4096), C.c_void_p(1 << 20), None) == -1
+
