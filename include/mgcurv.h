@@ -89,6 +89,11 @@ typedef struct {
 
 typedef struct mg_curv_ctx mg_curv_ctx;
 
+/* Identifier of the sources the library was built from (a hash of its
+ * source files and this header, fixed at build time); "unknown" for a build
+ * that did not set it.  Lets a loader refuse a stale binary.  Never NULL. */
+const char *mg_curv_build_id(void);
+
 /* Fill *p with the defaults for an H x W image: alpha 20, mean curvature,
  * levels 0 (automatic), float state, 4 fine colours, M = 16, G = 32, half
  * V-cycle, power-of-two blocks. */
@@ -295,6 +300,18 @@ mg_status mg_cnn_train_step(mg_cnn *c, const float *f, const float *target, int3
  * nullable) without updating the parameters.  Waits. */
 mg_status mg_cnn_gradients(mg_cnn *c, const float *f, const float *target, int32_t n, int32_t height, int32_t width,
                            double *loss, float *host_grads);
+
+/* One forward and backward pass as mg_cnn_gradients (no update), exporting the
+ * backward pass's intermediate gradients for inspection: host_dz (host,
+ * 5 x n x height x width x 32 bfloat16, NHWC, layer-major) receives
+ * dL/dz_l for l = 0..4, z_l being the pre-activation of layer l (so a_{l+1} =
+ * relu(z_l)), with the ReLU mask applied and rounded to bfloat16 as stored;
+ * host_dz5 (host, n x height x width floats) receives dL/dz_5 = 2 (u - target) /
+ * (n height width); host_grads (nullable) the parameter gradient.  The
+ * activations of the same forward pass are then available from
+ * mg_cnn_activation.  Waits. */
+mg_status mg_cnn_gradient_trace(mg_cnn *c, const float *f, const float *target, int32_t n, int32_t height,
+                                int32_t width, void *host_dz, float *host_dz5, float *host_grads);
 
 /* Copy the first `count` bfloat16 values of activation a_layer (layer 1..5,
  * NHWC with 32 channels) of the last forward pass to a host buffer. */

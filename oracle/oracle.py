@@ -19,12 +19,15 @@ def lib_path() -> str:
     return os.environ.get("MGC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (-O2, FP64, OpenMP; no fast-math)."""
-    out = lib_path()
+def build(force: bool = True, out: str | None = None, native: bool = False) -> str:
+    """Compile the oracle library with gcc (FP64, OpenMP; no fast-math, no FMA contraction, so the
+    results do not depend on the flags): -O2 for the portable build the tests load, or
+    -O3 -march=native for a copy timed on the machine that builds it (out = its path)."""
+    out = out or lib_path()
     if force or _stale(out):
         tmp = out + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+        opt = ["-O3", "-march=native"] if native else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=c99", "-fPIC", "-shared", "-fopenmp",
                                "-fno-fast-math", "-ffp-contract=off", *SOURCES, "-o", tmp, "-lm"])
         os.replace(tmp, out)
     return out

@@ -27,6 +27,19 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """Hash of everything the library is compiled from (csrc/ and include/mgcurv.h); the build
+    embeds it and the binding refuses a library built from other sources."""
+    import hashlib
+    h = hashlib.sha256()
+    paths = sorted(os.path.join(CSRC, n) for n in os.listdir(CSRC)) + [os.path.join(ROOT, "include", "mgcurv.h")]
+    for p in paths:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -41,9 +54,10 @@ def build(verbose: bool = False) -> str:
     cmds = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    tag = f'-DMGC_SOURCE_HASH="{source_hash()}"'
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmds.append([hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
+        cmds.append([hipcc(), *HIPCC_FLAGS, tag, "-I", os.path.join(ROOT, "include"), "-c",
                      os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for cmd in cmds:

@@ -384,48 +384,75 @@ __global__ __launch_bounds__(256) void out_dgrad_kernel(const float* __restrict_
     }
 }
 
-// Weight gradients of the VALU layers, per-workgroup partials (fixed pixel ranges).
-// Output layer: thread t < 288 handles (tap, i) = (t / 32, t % 32); t = 288 the bias.
-// Input layer:  thread t < 288 handles (tap, o) = (t / 32, t % 32); t in [288, 320) the bias of o = t - 288.
-__global__ __launch_bounds__(320) void small_wgrad_kernel(const bf16* __restrict__ act, const float* __restrict__ f,
-                                                          const float* __restrict__ dz5, const bf16* __restrict__ dz0,
-                                                          float* __restrict__ partials, int N, int H, int W,
-                                                          int input_layer, int px_per_block)
+// Weight gradients of the two VALU layers, which pair a 32-channel bfloat16 field V with a
+// scalar field S over the 3x3 taps:
+//   output layer (32 -> 1): dW5[tap][i] = sum_q a5[q][i] dz5[q - off(tap)],  db5 = sum_p dz5[p]
+//                           (V = a5, S = dz5, taps read S at q - off)
+//   input layer (1 -> 32):  dW0[tap][o] = sum_p dz0[p][o] f[p + off(tap)],   db0[o] = sum_p dz0[p][o]
+//                           (V = dz0, S = f, taps read S at p + off)
+// with S zero outside the image.  A persistent grid of workgroups walks 8 x 64 pixel tiles; the
+// tile's scalar field (with a one-pixel halo) is staged in LDS, and thread (channel ch = tid % 32,
+// row slot = tid / 32) accumulates the nine taps and the bias for its channel over its row of
+// every tile (one coalesced 64-byte read of V per pixel and warp of 32 lanes).  The eight row slots
+// are then added in a fixed order and each workgroup writes its partial sums:
+//   output layer: partials[wg * 289 + tap * 32 + i], bias at 288;
+//   input layer:  partials[wg * 320 + tap * 32 + o], bias of o at 288 + o.
+constexpr int SW_TH = 8, SW_TW = 64;
+__global__ __launch_bounds__(256) void scalar_wgrad_kernel(const bf16* __restrict__ vfield,
+                                                           const float* __restrict__ sfield,
+                                                           float* __restrict__ partials, int N, int H, int W,
+                                                           int input_layer)
 {
-    const int t = threadIdx.x;
-    const size_t total = (size_t)N * H * W;
-    const size_t p0 = (size_t)blockIdx.x * px_per_block;
-    size_t p1 = p0 + px_per_block;
-    if (p1 > total) p1 = total;
-    float acc = 0.0f;
-    if (!input_layer) {
-        if (t <= 288) {
-            const int tap = t / 32, ch = t % 32;
-            for (size_t p = p0; p < p1; ++p) {
-                const float d = dz5[p];
-                if (t == 288) { acc += d; continue; }
-                const int n = (int)(p / ((size_t)H * W));
-                const int rem = (int)(p - (size_t)n * H * W);
-                const int i = rem / W + tap / 3 - 1, j = rem % W + tap % 3 - 1;
-                if (i < 0 || i >= H || j < 0 || j >= W) continue;
-                acc = fmaf(from_bf16(act[(((size_t)n * H + i) * W + j) * C + ch]), d, acc);
-            }
-            partials[(size_t)blockIdx.x * 289 + t] = acc;
+    __shared__ float st[SW_TH + 2][SW_TW + 2];
+    __shared__ float red[8][C][10];
+    const int tid = threadIdx.x, ch = tid & 31, slot = tid >> 5;
+    const int tiles_x = (W + SW_TW - 1) / SW_TW, tiles_y = (H + SW_TH - 1) / SW_TH;
+    const int ntiles = N * tiles_x * tiles_y;
+    const int sgn = input_layer ? 1 : -1;
+    float acc[9], bacc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int n = tile / (tiles_x * tiles_y);
+        const int trem = tile - n * tiles_x * tiles_y;
+        const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
+        const int r0 = ty * SW_TH, c0 = tx * SW_TW;
+        const float* sf = sfield + (size_t)n * H * W;
+        __syncthreads();
+        for (int q = tid; q < (SW_TH + 2) * (SW_TW + 2); q += 256) {
+            const int rr = q / (SW_TW + 2), cc = q - rr * (SW_TW + 2);
+            const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
+            st[rr][cc] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? sf[(size_t)gi * W + gj] : 0.0f;
         }
-    } else {
-        if (t < 320) {
-            const int tap = t < 288 ? t / 32 : -1, o = t < 288 ? t % 32 : t - 288;
-            for (size_t p = p0; p < p1; ++p) {
-                const float d = from_bf16(dz0[p * C + o]);
-                if (tap < 0) { acc += d; continue; }
-                const int n = (int)(p / ((size_t)H * W));
-                const int rem = (int)(p - (size_t)n * H * W);
-                const int i = rem / W + tap / 3 - 1, j = rem % W + tap % 3 - 1;
-                if (i < 0 || i >= H || j < 0 || j >= W) continue;
-                acc = fmaf(f[((size_t)n * H + i) * W + j], d, acc);
+        __syncthreads();
+        const int gi = r0 + slot;
+        if (gi < H) {
+            const bf16* vrow = vfield + (((size_t)n * H + gi) * W) * C + ch;
+            const int cend = min(SW_TW, W - c0);
+            for (int cc = 0; cc < cend; ++cc) {
+                const float v = from_bf16(vrow[(size_t)(c0 + cc) * C]);
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    const int dy = t / 3 - 1, dx = t % 3 - 1;
+                    acc[t] = fmaf(v, st[1 + slot + sgn * dy][1 + cc + sgn * dx], acc[t]);
+                }
+                bacc += input_layer ? v : st[1 + slot][1 + cc];
             }
-            partials[(size_t)blockIdx.x * 320 + t] = acc;
         }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) red[slot][ch][t] = acc[t];
+    red[slot][ch][9] = bacc;
+    __syncthreads();
+    const int stride = input_layer ? 320 : 289;
+    float* out = partials + (size_t)blockIdx.x * stride;
+    for (int k = tid; k < C * 10; k += 256) {
+        const int c = k / 10, t = k - c * 10;
+        float s = 0.0f;
+        for (int r = 0; r < 8; ++r) s += red[r][c][t];
+        if (t < 9) out[t * C + c] = s;
+        else if (input_layer) out[288 + c] = s;
+        else if (c == 0) out[288] = s;
     }
 }
 
@@ -518,6 +545,7 @@ namespace {
 
 thread_local std::string g_cnn_error;
 constexpr int WG32 = 512;       // workgroups of the MFMA weight-gradient kernel
+constexpr int SW_WG = 256;      // workgroups of the scalar-field weight-gradient kernel
 constexpr int LOSS_BLOCKS = 1024;
 
 mg_status cfail(mg_cnn* c, mg_status st, const char* fmt, ...)
@@ -567,21 +595,33 @@ mg_status forward(mg_cnn* c, const float* f, float* u, const float* target, int 
     return e == hipSuccess ? MG_OK : chip(c, e, "forward");
 }
 
-// Backward pass into c->g (flat layout), after forward(..., target).
-mg_status backward(mg_cnn* c, const float* f, int n, int H, int W)
+// Backward pass into c->g (flat layout), after forward(..., target).  With trace_dz set (host,
+// 5 x n H W x 32 bfloat16) the gradients dL/dz_l of the hidden layers' pre-activations
+// (l = 0..4, ReLU mask applied) are copied out in layer order as they are produced, and
+// with trace_dz5 set (host, n H W floats) dL/dz_5 of the output layer.
+mg_status backward(mg_cnn* c, const float* f, int n, int H, int W, void* trace_dz = nullptr, float* trace_dz5 = nullptr)
 {
     const size_t total = (size_t)n * H * W;
     hipError_t e;
     const int tiles = n * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
     // output layer: weight gradient partials and dz4
-    const int pxb = 4096;
-    const int nb_small = (int)((total + pxb - 1) / pxb);
-    hipLaunchKernelGGL(small_wgrad_kernel, dim3(nb_small), dim3(320), 0, c->stream, c->act[4], f, c->dz5,
-                       (const bf16*)nullptr, c->part, n, H, W, 0, pxb);
+    const int stiles = n * ((H + SW_TH - 1) / SW_TH) * ((W + SW_TW - 1) / SW_TW);
+    const int nb_small = stiles < SW_WG ? stiles : SW_WG;
+    hipLaunchKernelGGL(scalar_wgrad_kernel, dim3(nb_small), dim3(256), 0, c->stream, c->act[4], c->dz5, c->part,
+                       n, H, W, 0);
     hipLaunchKernelGGL(sum_partials_f32, dim3((289 + 255) / 256), dim3(256), 0, c->stream, c->part, nb_small, 289, 289,
                        c->g + woff(NL - 1));
     hipLaunchKernelGGL(out_dgrad_kernel, dim3(grid_for(total)), dim3(256), 0, c->stream, c->dz5, c->act[4], c->W5q,
                        c->dzA, n, H, W);
+    auto trace = [&](const bf16* src, int layer) -> hipError_t {
+        if (!trace_dz) return hipSuccess;
+        return hipMemcpyAsync((bf16*)trace_dz + (size_t)layer * total * C, src, sizeof(bf16) * total * C,
+                              hipMemcpyDeviceToHost, c->stream);
+    };
+    if (trace_dz5 && (e = hipMemcpyAsync(trace_dz5, c->dz5, sizeof(float) * total, hipMemcpyDeviceToHost,
+                                         c->stream)) != hipSuccess)
+        return chip(c, e, "trace copy");
+    if ((e = trace(c->dzA, 4)) != hipSuccess) return chip(c, e, "trace copy");
     bf16* dz = c->dzA;
     bf16* other = c->dzB;
     for (int l = 4; l >= 1; --l) {
@@ -593,11 +633,11 @@ mg_status backward(mg_cnn* c, const float* f, int n, int H, int W)
         // input gradient through layer l, masked by a_l > 0 (the ReLU of layer l - 1)
         hipLaunchKernelGGL(conv32_kernel<true>, dim3(tiles), dim3(256), 0, c->stream, dz, other,
                            c->Wb + (size_t)(l - 1) * 9 * C * C, (const float*)nullptr, c->act[l - 1], n, H, W);
+        if ((e = trace(other, l - 1)) != hipSuccess) return chip(c, e, "trace copy");
         bf16* t = dz; dz = other; other = t;
     }
     // input layer: weight gradient from f and dz0
-    hipLaunchKernelGGL(small_wgrad_kernel, dim3(nb_small), dim3(320), 0, c->stream, (const bf16*)nullptr, f,
-                       (const float*)nullptr, dz, c->part, n, H, W, 1, pxb);
+    hipLaunchKernelGGL(scalar_wgrad_kernel, dim3(nb_small), dim3(256), 0, c->stream, dz, f, c->part, n, H, W, 1);
     hipLaunchKernelGGL(sum_partials_f32, dim3((320 + 255) / 256), dim3(256), 0, c->stream, c->part, nb_small, 320, 288,
                        c->g + woff(0));
     hipLaunchKernelGGL(sum_partials_f32, dim3(1), dim3(32), 0, c->stream, c->part + 288, nb_small, 320, 32, c->g + boff(0));
@@ -634,10 +674,7 @@ mg_status mg_cnn_init(int64_t max_pixels, void* hip_stream, mg_cnn** out)
     c->maxpix = (int)max_pixels;
     c->stream = (hipStream_t)hip_stream;
     const size_t P = (size_t)max_pixels;
-    const size_t tiles_cap = P / 16 + 1024;   // generous bound on 8 x 32 tiles incl. ragged edges
-    (void)tiles_cap;
-    const size_t nb_small = (P + 4095) / 4096 + 1;
-    c->part_cap = std::max<size_t>((size_t)WG32 * (9 * C * C + C), nb_small * 320);
+    c->part_cap = std::max<size_t>((size_t)WG32 * (9 * C * C + C), (size_t)SW_WG * 320);
     bool ok = true;
     auto al = [&](void** p, size_t bytes) { if (ok && hipMalloc(p, bytes ? bytes : 1) != hipSuccess) ok = false; };
     al((void**)&c->w, sizeof(float) * NPARAM);
@@ -714,6 +751,21 @@ mg_status mg_cnn_gradients(mg_cnn* c, const float* f, const float* target, int32
         hipError_t e = hipMemcpy(host_grads, c->g, sizeof(float) * NPARAM, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return chip(c, e, "gradient copy");
     }
+    return MG_OK;
+}
+
+mg_status mg_cnn_gradient_trace(mg_cnn* c, const float* f, const float* target, int32_t n, int32_t height,
+                                int32_t width, void* host_dz, float* host_dz5, float* host_grads)
+{
+    mg_status st = check_shape(c, n, height, width);
+    if (st != MG_OK) return st;
+    if (!f || !target || !host_dz || !host_dz5) return cfail(c, MG_E_INVALID, "f, target, host_dz and host_dz5 must be non-null");
+    if ((st = forward(c, f, c->upred, target, n, height, width)) != MG_OK) return st;
+    if ((st = backward(c, f, n, height, width, host_dz, host_dz5)) != MG_OK) return st;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return chip(c, e, "synchronize");
+    if (host_grads && (e = hipMemcpy(host_grads, c->g, sizeof(float) * NPARAM, hipMemcpyDeviceToHost)) != hipSuccess)
+        return chip(c, e, "gradient copy");
     return MG_OK;
 }
 

@@ -219,6 +219,11 @@ hipError_t noalloc_scratch(int device, double** out)
 
 extern "C" {
 
+#ifndef MGC_SOURCE_HASH
+#define MGC_SOURCE_HASH "unknown"
+#endif
+const char* mg_curv_build_id(void) { return MGC_SOURCE_HASH; }
+
 void mg_curv_default_params(mg_curv_params* p, int32_t height, int32_t width)
 {
     if (!p) return;

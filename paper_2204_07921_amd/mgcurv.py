@@ -54,6 +54,13 @@ def _load() -> C.CDLL:
         from . import build as _b
         _b.build()
     L = C.CDLL(LIB_PATH)
+    L.mg_curv_build_id.restype = C.c_char_p
+    L.mg_curv_build_id.argtypes = []
+    from . import build as _b
+    want, got = _b.source_hash(), L.mg_curv_build_id().decode()
+    if got != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (build id {got}, sources {want}); "
+                          "rebuild it with: python -m paper_2204_07921_amd.build")
     P = C.POINTER(MgCurvParams)
     vp, cvp = C.c_void_p, C.c_void_p
     L.mg_curv_default_params.restype = None
@@ -125,6 +132,8 @@ def _load() -> C.CDLL:
     L.mg_cnn_train_step.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.POINTER(C.c_double)]
     L.mg_cnn_gradients.restype = C.c_int
     L.mg_cnn_gradients.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+    L.mg_cnn_gradient_trace.restype = C.c_int
+    L.mg_cnn_gradient_trace.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
     L.mg_cnn_activation.restype = C.c_int
     L.mg_cnn_activation.argtypes = [vp, C.c_int32, vp, C.c_int64]
     L.mg_cnn_destroy.restype = None
@@ -705,6 +714,19 @@ class WarmStartCNN:
         _ccheck(lib.mg_cnn_gradients(self.c, self._img(f, "f"), self._img(target, "target"), n, h, w,
                                      C.byref(loss), g.ctypes.data), self.c)
         return loss.value, g
+
+    def gradient_trace(self, f: torch.Tensor, target: torch.Tensor):
+        """Intermediate gradients of one backward pass: ([dL/dz_l for l = 0..4] as float32 numpy
+        (n, h, w, 32) from their bfloat16 storage, dL/dz_5 as (n, h, w), parameter gradient)."""
+        import numpy as np
+        n, h, w = f.shape
+        raw = np.empty(5 * n * h * w * 32, dtype=np.uint16)
+        dz5 = np.empty(n * h * w, dtype=np.float32)
+        g = np.empty(self.n_params, dtype=np.float32)
+        _ccheck(lib.mg_cnn_gradient_trace(self.c, self._img(f, "f"), self._img(target, "target"), n, h, w,
+                                          raw.ctypes.data, dz5.ctypes.data, g.ctypes.data), self.c)
+        dz = (raw.astype(np.uint32) << 16).view(np.float32).reshape(5, n, h, w, 32)
+        return [dz[l] for l in range(5)], dz5.reshape(n, h, w), g
 
     def activation(self, layer: int, shape):
         """Activation a_layer (1..5) of the last forward pass as float32 numpy (n, h, w, 32)."""

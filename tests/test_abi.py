@@ -301,3 +301,15 @@ def test_energy_noalloc_validates_before_device(lib, field, value, status):
                                       C.c_void_p(1 << 24)) == -1
     assert lib.mg_curv_energy_noalloc(C.byref(p), None, C.c_void_p(4096), C.c_void_p(1 << 20), None) == -1
 
+
+def test_library_carries_its_source_hash(lib):
+    from paper_2204_07921_amd import build
+    lib.mg_curv_build_id.restype = C.c_char_p
+    assert lib.mg_curv_build_id().decode() == build.source_hash()
+
+
+def test_binding_refuses_a_stale_library(monkeypatch):
+    from paper_2204_07921_amd import build, mgcurv
+    monkeypatch.setattr(build, "source_hash", lambda: "0" * 16)
+    with pytest.raises(ImportError, match="built from other sources"):
+        mgcurv._load()

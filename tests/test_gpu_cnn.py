@@ -4,8 +4,9 @@ Tolerances follow from bfloat16 storage: both sides round weights, activations a
 gradients to bfloat16 at the same points (round to nearest even); the GPU accumulates in FP32,
 the reference in FP64, so a stored value can land one bfloat16 step (2^-8 relative) away when
 the two accumulations straddle a rounding boundary.  Layers are compared from the GPU's own
-inputs (teacher forcing) so such steps do not compound; gradients are compared by relative
-norm and direction per layer."""
+inputs (teacher forcing) so such steps do not compound.  The backward pass is compared element by
+element in the same way (each layer from the GPU's own gradient of the layer above), and the
+end-to-end parameter gradient by relative norm and direction per layer."""
 import numpy as np
 import pytest
 import torch
@@ -89,6 +90,60 @@ def test_gradients_match_reference(mg):
         cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
         print(f"layer {l}: relative gradient error {rel:.2e}, cosine {cos:.6f}")
         assert rel <= 2e-2 and cos >= 0.9995, (l, rel, cos)
+
+
+@pytest.mark.parametrize("shape", [(2, 24, 40), (1, 19, 70), (3, 9, 33)])
+def test_backward_per_layer_matches_reference(mg, shape):
+    """Element-wise, teacher-forced backward pass.  From the GPU's own activations and its own
+    gradient of each layer's output, the FP64 reference computes that layer's input gradient (3x3
+    transposed convolution with the bfloat16 weights, ReLU mask, bfloat16 rounding) and its weight
+    and bias gradients; every element is compared.  Input gradients may differ by one bfloat16 step
+    (FP32 vs FP64 accumulation straddling a rounding boundary); weight gradients by the FP32
+    accumulation error, at most 1e-4 of the sum of the absolute products of each element."""
+    n, h, w = shape
+    _case(f"backward per layer {shape}")
+    f = np.stack(_batch([(h, w)] * n, seed=40))
+    target = (f + 0.05 * np.cos(0.3 * np.arange(w))[None, None, :] - 0.02).astype(np.float32)
+    p = _params(4)
+    net = mg.WarmStartCNN(n * h * w, p)
+    fd, td = torch.tensor(f, device="cuda"), torch.tensor(target, device="cuda")
+    u = net.forward(fd).cpu().numpy()
+    dz, dz5, g = net.gradient_trace(fd, td)
+    acts = [f[..., None].astype(np.float64)] + [net.activation(l, (n, h, w)).astype(np.float64) for l in range(1, 6)]
+    layers = cnn_ref.unpack(p)
+    # output gradient of the loss: 2 (u - target) / N from the GPU's own prediction, in float32
+    r32 = (u - target).astype(np.float32).astype(np.float64)
+    ref5 = 2.0 * r32 / (n * h * w)
+    assert np.max(np.abs(dz5 - ref5)) <= 2.0 ** -23 * np.max(np.abs(ref5)), np.max(np.abs(dz5 - ref5))
+    # input gradients, layer by layer from the GPU's gradient of the layer above
+    g_up = dz5.astype(np.float64)[..., None]
+    for l in range(5, 0, -1):
+        W, _ = layers[l]
+        ref = cnn_ref.round_bf16(cnn_ref.conv_transpose_taps(g_up, cnn_ref.round_bf16(W)) * (acts[l] > 0))
+        got = dz[l - 1].astype(np.float64)
+        step = 2.0 ** -7 * np.abs(ref) + 1e-4 * np.max(np.abs(ref))
+        bad = np.abs(got - ref) > step
+        print(f"dz_{l - 1}: max |got - ref| {np.max(np.abs(got - ref)):.3e}, "
+              f"elements off by a bfloat16 step {np.count_nonzero(got != ref)} of {ref.size}")
+        assert np.count_nonzero(bad) == 0, (l, np.max(np.abs(got - ref)))
+        # a wrong tap or channel would move most elements; rounding-boundary splits stay rare
+        assert np.count_nonzero(got != ref) <= max(4, ref.size // 50), l
+        g_up = got
+    # weight and bias gradients of every layer from the GPU's inputs and output gradients
+    for l, sl in enumerate(LAYER_SLICES):
+        a = acts[l]
+        d = dz5.astype(np.float64)[..., None] if l == 5 else dz[l].astype(np.float64)
+        refW = cnn_ref.weight_grad(a, d)
+        absW = cnn_ref.weight_grad(np.abs(a), np.abs(d))
+        refb = d.sum(axis=(0, 1, 2))
+        absb = np.abs(d).sum(axis=(0, 1, 2))
+        gl = g[sl].astype(np.float64)
+        gotW, gotb = gl[:refW.size].reshape(refW.shape), gl[refW.size:]
+        errW = np.abs(gotW - refW) / (absW + 1e-30)
+        errb = np.abs(gotb - refb) / (absb + 1e-30)
+        print(f"layer {l}: weight gradient max error {errW.max():.2e}, bias {errb.max():.2e} of the absolute sums")
+        assert np.all(np.abs(gotW - refW) <= 1e-4 * absW + 1e-12), (l, errW.max())
+        assert np.all(np.abs(gotb - refb) <= 1e-4 * absb + 1e-12), (l, errb.max())
 
 
 def test_adam_step_matches_reference(mg):

@@ -13,6 +13,7 @@ Tolerances, derived from the arithmetic:
   * Energy: two summation orders of N non-negative terms differ by at most
     about 2 N eps relative.
 """
+import json
 import os
 
 import numpy as np
@@ -151,11 +152,19 @@ def _trajectory(mg, orc, h, w, kind, colours, dtype, cycles, seed, sigma, levels
     return e_gpu, trace[-1], du
 
 
-# Free-running energies: the oracle run against itself with 1e-15 relative input perturbations
-# (seeds 0-2, six perturbations each) moves the 20-cycle energy by up to 1.2e-6 relative, with a
-# heavy tail from discrete basin changes; the GPU trajectory, checked sweep by sweep above, is held
-# to 2e-5.
-FREE_RUN_ENERGY_TOL = 2e-5
+# Free-running energies.  The 20-cycle energy of this nonconvex, chaotic iteration moves when the
+# state changes at the rounding level: tests/golden/free_run_spread.json holds, per case, the
+# relative spread of the oracle's own 20-cycle energy over 200 runs from u_0 = f (1 + 1e-15 z)
+# (written by tests/golden/free_run_spread.py, which calls only the oracle).  The GPU computes its
+# sums in another order, so its energy is one more draw from that spread; it is held to 1.5 times
+# the largest of the 200 (for seed 1 of the mean-curvature case that is 1.2e-5, for the others
+# 1.5e-7 .. 1.3e-6).
+_SPREAD = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "free_run_spread.json")))["cases"]
+
+
+def free_run_tol(name):
+    return 1.5 * _SPREAD[name]["rel_spread"]["max"]
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -165,14 +174,17 @@ def test_config_64_mean_fp64_20_vcycles(mg, orc, seed):
     energies agree to the amplification level the oracle itself shows under a 1e-15 perturbation."""
     _case(f"64x64 MC fp64 seed={seed}")
     e_gpu, e_orc, du = _trajectory(mg, orc, 64, 64, 0, 4, torch.float64, 20, seed, 0.05, levels=6)
-    assert abs(e_gpu - e_orc) <= FREE_RUN_ENERGY_TOL * e_orc
+    print(f"free-running energy gap {abs(e_gpu - e_orc) / e_orc:.3e}, tolerance {free_run_tol(f'mean_4_seed{seed}'):.3e}")
+    assert abs(e_gpu - e_orc) <= free_run_tol(f"mean_4_seed{seed}") * e_orc
 
 
 @pytest.mark.parametrize("kind,colours", [(1, 4), (0, 9), (1, 9)])
 def test_config_64_variants_fp64(mg, orc, kind, colours):
     _case(f"64x64 kind={kind} colours={colours} fp64")
     e_gpu, e_orc, du = _trajectory(mg, orc, 64, 64, kind, colours, torch.float64, 20, 0, 0.05, levels=6)
-    assert abs(e_gpu - e_orc) <= FREE_RUN_ENERGY_TOL * e_orc
+    name = f"{'gauss' if kind else 'mean'}_{colours}_seed0"
+    print(f"free-running energy gap {abs(e_gpu - e_orc) / e_orc:.3e}, tolerance {free_run_tol(name):.3e}")
+    assert abs(e_gpu - e_orc) <= free_run_tol(name) * e_orc
 
 
 @pytest.mark.parametrize("kind", [0, 1])
