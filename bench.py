@@ -100,12 +100,15 @@ def parse():
     return ap.parse_args()
 
 
+# the sources the colour-sweep kernels are compiled from (their counters are void once these change)
+SWEEP_SOURCES = ("mgc_device.h", "mgc_internal.h", "mgc_sweep.h", "mgc_kernels.hip")
+
+
 def kernel_sources_sha() -> str:
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2204_07921_amd", "csrc", "*"))):
-        with open(p, "rb") as fh:
+    for name in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2204_07921_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -163,8 +166,47 @@ def warm_start_measure(fd, plain: dict, warm_batch: int) -> dict:
     if warm_batch:
         fe = warmstart.make_inputs(warm_batch, H, seed0=100000)
         net8 = mgcurv.WarmStartCNN(8 * H * W, params)
+        out["cnn_inference"] = cnn_inference_measure(net8, fe)
         out["batch"] = warmstart.evaluate(net8, fe)
+        # the nine-colour pixel level as the plain solver: it settles far lower, the network's
+        # prediction starts above its energy, and the warm start has to refine
+        nine = warmstart.evaluate_single(net8, fe, fine_colours=9)
+        nine.pop("per_image")
+        out["batch_nine_colours"] = nine
     return out
+
+
+# Warm-start CNN inference per pixel: 4 hidden 32 -> 32 layers of 9 x 32 x 32 multiply-adds on the
+# matrix cores, the 1 -> 32 and 32 -> 1 layers (9 x 32 each) on the vector units.  Bytes per pixel
+# with the layers unfused (bfloat16 activations, 32 channels = 64 B): input layer 4 B in + 64 B
+# out, each hidden layer 64 B in + 64 B out, output layer 64 B + 4 B (f) in + 4 B out.
+CNN_MFMA_FLOPS_PX = 4 * 2 * 9 * 32 * 32
+CNN_VALU_FLOPS_PX = 2 * 2 * 9 * 32
+CNN_BYTES_PX = (4 + 64) + 4 * (64 + 64) + (64 + 4 + 4)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def cnn_inference_measure(net, f) -> dict:
+    """u0 = f + g(f) for a stack of 1024x1024 images in chunks of the network's capacity, HIP events on
+    the current stream; rates against the bfloat16 matrix-core peak and the HBM peak."""
+    import torch
+    from paper_2204_07921_amd import warmstart
+    warmstart.forward_chunked(net, f[:1].contiguous())
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    warmstart.forward_chunked(net, f)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    px = f.numel()
+    return {"images": int(f.shape[0]), "ms": round(ms, 3), "ms_per_image": round(ms / f.shape[0], 4),
+            "mfma_tflops": round(px * CNN_MFMA_FLOPS_PX / (ms * 1e-3) / 1e12, 2),
+            "mfma_frac": round(px * CNN_MFMA_FLOPS_PX / (ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4),
+            "algorithmic_gbs": round(px * CNN_BYTES_PX / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(px * CNN_BYTES_PX / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "counted_as": "matrix-core flops of the four 32->32 layers (2 x 9 x 32 x 32 per pixel each); "
+                          "bytes of unfused bfloat16 layers (652 B per pixel)"}
 
 
 def batch_measure(steps: int, solve: bool) -> dict:

@@ -288,6 +288,14 @@ mg_status mg_cnn_init(int64_t max_pixels, void *hip_stream, mg_cnn **out);
 mg_status mg_cnn_set_params(mg_cnn *c, const float *host_params);
 mg_status mg_cnn_get_params(mg_cnn *c, float *host_params);
 
+/* Training checkpoint: the FP32 parameters, both Adam moments (host arrays of
+ * mg_cnn_num_params floats each) and the Adam step count.  A context restored
+ * with mg_cnn_set_state continues training bit for bit as the one the state
+ * was read from would have.  Both wait for completion. */
+mg_status mg_cnn_get_state(mg_cnn *c, float *host_params, float *host_m, float *host_v, int32_t *step);
+mg_status mg_cnn_set_state(mg_cnn *c, const float *host_params, const float *host_m, const float *host_v,
+                           int32_t step);
+
 /* u = f + g(f) for n images (device pointers, u may not alias f).  Enqueued only. */
 mg_status mg_cnn_forward(mg_cnn *c, const float *f, float *u, int32_t n, int32_t height, int32_t width);
 

@@ -280,27 +280,40 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
                                                       const float* __restrict__ W0q, const float* __restrict__ b0,
                                                       int N, int H, int W)
 {
+    // the 288 weights and 32 biases in LDS (held in scalar registers they would spill)
+    __shared__ float sw[9 * C], sb[C];
+    for (int k = threadIdx.x; k < 9 * C; k += blockDim.x) sw[k] = W0q[k];
+    if (threadIdx.x < C) sb[threadIdx.x] = b0[threadIdx.x];
+    __syncthreads();
     const size_t total = (size_t)N * H * W;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
-        const int n = (int)(p / ((size_t)H * W));
-        const int rem = (int)(p - (size_t)n * H * W);
-        const int i = rem / W, j = rem - i * W;
+    // 32-bit index arithmetic (a batch holds fewer than 2^31 pixels); 64-bit only for addresses
+    const unsigned hw = (unsigned)H * (unsigned)W, tot = (unsigned)total;
+    for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+        const size_t p = q;
+        const unsigned n = q / hw;
+        const unsigned rem = q - n * hw;
+        const int i = (int)(rem / (unsigned)W), j = (int)(rem - (unsigned)i * (unsigned)W);
         float t[9];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int gi = i + tap / 3 - 1, gj = j + tap % 3 - 1;
             t[tap] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? f[((size_t)n * H + gi) * W + gj] : 0.0f;
         }
-        bf16x8 out[4];
+        // eight channels at a time; the group loop stays rolled so the weights are read from LDS
+        // as they are needed instead of all being held in registers
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            bf16x8 o8;
 #pragma unroll
-        for (int o = 0; o < C; ++o) {
-            float z = b0[o];
+            for (int e = 0; e < 8; ++e) {
+                const int o = 8 * k + e;
+                float z = sb[o];
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) z = fmaf(t[tap], W0q[tap * C + o], z);
-            out[o >> 3][o & 7] = to_bf16(fmaxf(z, 0.0f));
+                for (int tap = 0; tap < 9; ++tap) z = fmaf(t[tap], sw[tap * C + o], z);
+                o8[e] = to_bf16(fmaxf(z, 0.0f));
+            }
+            *reinterpret_cast<bf16x8*>(y + p * C + 8 * k) = o8;
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) *reinterpret_cast<bf16x8*>(y + p * C + 8 * k) = out[k];
     }
 }
 
@@ -318,10 +331,13 @@ __global__ __launch_bounds__(256) void conv_out_kernel(const bf16* __restrict__ 
     __shared__ double lds[4];
     const size_t total = (size_t)N * H * W;
     double lsum = 0.0;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
-        const int n = (int)(p / ((size_t)H * W));
-        const int rem = (int)(p - (size_t)n * H * W);
-        const int i = rem / W, j = rem - i * W;
+    // 32-bit index arithmetic (a batch holds fewer than 2^31 pixels); 64-bit only for addresses
+    const unsigned hw = (unsigned)H * (unsigned)W, tot = (unsigned)total;
+    for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+        const size_t p = q;
+        const unsigned n = q / hw;
+        const unsigned rem = q - n * hw;
+        const int i = (int)(rem / (unsigned)W), j = (int)(rem - (unsigned)i * (unsigned)W);
         float z = b5[0];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
@@ -356,11 +372,17 @@ __global__ __launch_bounds__(256) void out_dgrad_kernel(const float* __restrict_
                                                         const float* __restrict__ W5q, bf16* __restrict__ dz4,
                                                         int N, int H, int W)
 {
+    __shared__ float sw[9 * C];   // the weights in LDS (held in scalar registers they would spill)
+    for (int k = threadIdx.x; k < 9 * C; k += blockDim.x) sw[k] = W5q[k];
+    __syncthreads();
     const size_t total = (size_t)N * H * W;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += (size_t)gridDim.x * blockDim.x) {
-        const int n = (int)(p / ((size_t)H * W));
-        const int rem = (int)(p - (size_t)n * H * W);
-        const int i = rem / W, j = rem - i * W;
+    // 32-bit index arithmetic (a batch holds fewer than 2^31 pixels); 64-bit only for addresses
+    const unsigned hw = (unsigned)H * (unsigned)W, tot = (unsigned)total;
+    for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+        const size_t p = q;
+        const unsigned n = q / hw;
+        const unsigned rem = q - n * hw;
+        const int i = (int)(rem / (unsigned)W), j = (int)(rem - (unsigned)i * (unsigned)W);
         float d[9];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
@@ -368,15 +390,15 @@ __global__ __launch_bounds__(256) void out_dgrad_kernel(const float* __restrict_
             const int gi = i - (tap / 3 - 1), gj = j - (tap % 3 - 1);
             d[tap] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? dz5[((size_t)n * H + gi) * W + gj] : 0.0f;
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {   // rolled: the weights are read from LDS as needed
             const bf16x8 m = *reinterpret_cast<const bf16x8*>(a5 + p * C + 8 * k);
             bf16x8 o;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 float s = 0.0f;
 #pragma unroll
-                for (int tap = 0; tap < 9; ++tap) s = fmaf(d[tap], W5q[tap * C + 8 * k + e], s);
+                for (int tap = 0; tap < 9; ++tap) s = fmaf(d[tap], sw[tap * C + 8 * k + e], s);
                 o[e] = to_bf16(from_bf16(m[e]) > 0.0f ? s : 0.0f);
             }
             *reinterpret_cast<bf16x8*>(dz4 + p * C + 8 * k) = o;
@@ -456,14 +478,29 @@ __global__ __launch_bounds__(256) void scalar_wgrad_kernel(const bf16* __restric
     }
 }
 
-// grad[k] = sum over blocks b of partials[b * stride + k], in block order.
+// grad[k] = sum over blocks b of partials[b * stride + k] in two fixed-order passes: slice y
+// (blockIdx.y) adds the blocks [y chunk, (y + 1) chunk) in block order into part2[y * count + k],
+// then sum_slices_f32 adds the slices in slice order.
+constexpr int SUM_SLICES = 16;
 __global__ void sum_partials_f32(const float* __restrict__ partials, int nblocks, int stride, int count,
-                                 float* __restrict__ out)
+                                 float* __restrict__ part2)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int chunk = (nblocks + SUM_SLICES - 1) / SUM_SLICES;
+    const int b0 = blockIdx.y * chunk, b1 = min(b0 + chunk, nblocks);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += partials[(size_t)b * stride + k];
+    part2[(size_t)blockIdx.y * count + k] = s;
+}
+
+__global__ void sum_slices_f32(const float* __restrict__ part2, int count, float* __restrict__ out)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count) return;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * stride + k];
+#pragma unroll
+    for (int y = 0; y < SUM_SLICES; ++y) s += part2[(size_t)y * count + k];
     out[k] = s;
 }
 
@@ -533,6 +570,7 @@ struct mg_cnn {
     float* dz5 = nullptr;
     float* upred = nullptr;
     float* part = nullptr;     // weight-gradient partials
+    float* part2 = nullptr;    // their per-slice sums (SUM_SLICES x count)
     size_t part_cap = 0;
     double* loss_part = nullptr;
     double* loss_dev = nullptr;
@@ -570,6 +608,15 @@ mg_status check_shape(mg_cnn* c, int n, int H, int W)
 }
 
 int grid_for(size_t total) { size_t g = (total + 255) / 256; return (int)(g < 8192 ? g : 8192); }
+
+// out[k] = sum over the nblocks per-workgroup partials (stride apart) of element k, k < count.
+void sum_partials(mg_cnn* c, const float* partials, int nblocks, int stride, int count, float* out)
+{
+    const unsigned gx = (unsigned)((count + 255) / 256);
+    hipLaunchKernelGGL(sum_partials_f32, dim3(gx, SUM_SLICES), dim3(256), 0, c->stream, partials, nblocks, stride,
+                       count, c->part2);
+    hipLaunchKernelGGL(sum_slices_f32, dim3(gx), dim3(256), 0, c->stream, c->part2, count, out);
+}
 
 mg_status refresh(mg_cnn* c)
 {
@@ -609,8 +656,7 @@ mg_status backward(mg_cnn* c, const float* f, int n, int H, int W, void* trace_d
     const int nb_small = stiles < SW_WG ? stiles : SW_WG;
     hipLaunchKernelGGL(scalar_wgrad_kernel, dim3(nb_small), dim3(256), 0, c->stream, c->act[4], c->dz5, c->part,
                        n, H, W, 0);
-    hipLaunchKernelGGL(sum_partials_f32, dim3((289 + 255) / 256), dim3(256), 0, c->stream, c->part, nb_small, 289, 289,
-                       c->g + woff(NL - 1));
+    sum_partials(c, c->part, nb_small, 289, 289, c->g + woff(NL - 1));
     hipLaunchKernelGGL(out_dgrad_kernel, dim3(grid_for(total)), dim3(256), 0, c->stream, c->dz5, c->act[4], c->W5q,
                        c->dzA, n, H, W);
     auto trace = [&](const bf16* src, int layer) -> hipError_t {
@@ -628,8 +674,7 @@ mg_status backward(mg_cnn* c, const float* f, int n, int H, int W, void* trace_d
         // weight gradient of layer l: input a_l = act[l-1], output gradient dz
         const int nwg = tiles < WG32 ? tiles : WG32;
         hipLaunchKernelGGL(wgrad32_kernel, dim3(nwg), dim3(256), 0, c->stream, c->act[l - 1], dz, c->part, n, H, W);
-        hipLaunchKernelGGL(sum_partials_f32, dim3((9 * C * C + C + 255) / 256), dim3(256), 0, c->stream, c->part, nwg,
-                           9 * C * C + C, 9 * C * C + C, c->g + woff(l));
+        sum_partials(c, c->part, nwg, 9 * C * C + C, 9 * C * C + C, c->g + woff(l));
         // input gradient through layer l, masked by a_l > 0 (the ReLU of layer l - 1)
         hipLaunchKernelGGL(conv32_kernel<true>, dim3(tiles), dim3(256), 0, c->stream, dz, other,
                            c->Wb + (size_t)(l - 1) * 9 * C * C, (const float*)nullptr, c->act[l - 1], n, H, W);
@@ -638,9 +683,8 @@ mg_status backward(mg_cnn* c, const float* f, int n, int H, int W, void* trace_d
     }
     // input layer: weight gradient from f and dz0
     hipLaunchKernelGGL(scalar_wgrad_kernel, dim3(nb_small), dim3(256), 0, c->stream, dz, f, c->part, n, H, W, 1);
-    hipLaunchKernelGGL(sum_partials_f32, dim3((320 + 255) / 256), dim3(256), 0, c->stream, c->part, nb_small, 320, 288,
-                       c->g + woff(0));
-    hipLaunchKernelGGL(sum_partials_f32, dim3(1), dim3(32), 0, c->stream, c->part + 288, nb_small, 320, 32, c->g + boff(0));
+    sum_partials(c, c->part, nb_small, 320, 288, c->g + woff(0));
+    sum_partials(c, c->part + 288, nb_small, 320, 32, c->g + boff(0));
     e = hipGetLastError();
     return e == hipSuccess ? MG_OK : chip(c, e, "backward");
 }
@@ -691,6 +735,7 @@ mg_status mg_cnn_init(int64_t max_pixels, void* hip_stream, mg_cnn** out)
     al((void**)&c->dz5, sizeof(float) * P);
     al((void**)&c->upred, sizeof(float) * P);
     al((void**)&c->part, sizeof(float) * c->part_cap);
+    al((void**)&c->part2, sizeof(float) * SUM_SLICES * (9 * C * C + C));
     al((void**)&c->loss_part, sizeof(double) * LOSS_BLOCKS);
     al((void**)&c->loss_dev, sizeof(double));
     if (ok && hipHostMalloc((void**)&c->loss_host, sizeof(double), hipHostMallocDefault) != hipSuccess) ok = false;
@@ -726,6 +771,33 @@ mg_status mg_cnn_get_params(mg_cnn* c, float* host_params)
     hipError_t e = hipMemcpyAsync(host_params, c->w, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return e == hipSuccess ? MG_OK : chip(c, e, "parameter copy");
+}
+
+mg_status mg_cnn_get_state(mg_cnn* c, float* host_params, float* host_m, float* host_v, int32_t* step)
+{
+    if (!c || !host_params || !host_m || !host_v || !step) return MG_E_INVALID;
+    hipError_t e = hipMemcpyAsync(host_params, c->w, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_m, c->m, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_v, c->v, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return chip(c, e, "state copy");
+    *step = c->step;
+    return MG_OK;
+}
+
+mg_status mg_cnn_set_state(mg_cnn* c, const float* host_params, const float* host_m, const float* host_v, int32_t step)
+{
+    if (!c || !host_params || !host_m || !host_v) return MG_E_INVALID;
+    if (step < 0) return cfail(c, MG_E_INVALID, "step must be >= 0");
+    hipError_t e = hipMemcpyAsync(c->w, host_params, sizeof(float) * NPARAM, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->m, host_m, sizeof(float) * NPARAM, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->v, host_v, sizeof(float) * NPARAM, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return chip(c, e, "state copy");
+    c->step = step;
+    mg_status st = refresh(c);
+    if (st != MG_OK) return st;
+    e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? MG_OK : chip(c, e, "synchronize");
 }
 
 mg_status mg_cnn_forward(mg_cnn* c, const float* f, float* u, int32_t n, int32_t height, int32_t width)
@@ -807,7 +879,7 @@ void mg_cnn_destroy(mg_cnn* c)
     if (!c) return;
     if (c->stream || c->w) (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = {c->w, c->g, c->m, c->v, c->W0q, c->W5q, c->Wf, c->Wb, c->act[0], c->act[1], c->act[2], c->act[3],
-                    c->act[4], c->dzA, c->dzB, c->dz5, c->upred, c->part, c->loss_part, c->loss_dev};
+                    c->act[4], c->dzA, c->dzB, c->dz5, c->upred, c->part, c->part2, c->loss_part, c->loss_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->loss_host) (void)hipHostFree(c->loss_host);

@@ -41,8 +41,15 @@ __global__ __launch_bounds__(256) void sweep_pixels_kernel(const T* __restrict__
         solve_ring_cell<T, KIND, NC>(uin, uout, f, H, W, colour, cr, cc, lane, alpha, M, G);
         return;
     }
+    // interior workgroups: the dispatcher hands workgroups to the 8 XCDs round-robin (workgroup b
+    // of the interior to XCD b % 8, ring_blocks being a multiple of 8); each XCD takes one
+    // contiguous run of cell rows, so neighbouring cells share their halo rows in one XCD's L2
+    // instead of every XCD fetching them
     const int ir = cells_r - 2, ic = cells_c - 2;
-    const int cell = (blockIdx.x - ring_blocks) * blockDim.x + threadIdx.x;
+    const int nb_in = (int)gridDim.x - ring_blocks, b = (int)blockIdx.x - ring_blocks;
+    const int x = b & 7, q = nb_in >> 3, r = nb_in & 7;
+    const int run = x * q + min(x, r) + (b >> 3);
+    const int cell = run * blockDim.x + threadIdx.x;
     if (ir <= 0 || ic <= 0 || cell >= ir * ic) return;
     const int cr = 1 + cell / ic, cc = 1 + cell % ic;
     solve_cell<T, KIND, NC, 1>(uin, uout, f, H, W, colour, cr, cc, alpha, M, G);
@@ -215,7 +222,7 @@ static hipError_t launch_pixels_nc(const LaunchCtx& L, const void* uin, void* uo
 {
     const int cells_r = (L.H + NC - 1) / NC, cells_c = (L.W + NC - 1) / NC;
     const int n_in = (cells_r > 2 && cells_c > 2) ? (cells_r - 2) * (cells_c - 2) : 0;
-    const int rb = (ring_cell_count(cells_r, cells_c) * 16 + 255) / 256;
+    const int rb = ((ring_cell_count(cells_r, cells_c) * 16 + 255) / 256 + 7) & ~7;   // a multiple of 8
     hipLaunchKernelGGL((sweep_pixels_kernel<T, KIND, NC>), dim3(rb + (n_in + 255) / 256), dim3(256), 0, L.stream,
                        (const T*)uin, (T*)uout, (const T*)f, L.H, L.W, colour, cells_r, cells_c, rb, L.alpha, L.M, L.G);
     return hipGetLastError();

@@ -132,6 +132,10 @@ def _load() -> C.CDLL:
     L.mg_cnn_train_step.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.POINTER(C.c_double)]
     L.mg_cnn_gradients.restype = C.c_int
     L.mg_cnn_gradients.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
+    L.mg_cnn_get_state.restype = C.c_int
+    L.mg_cnn_get_state.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int32)]
+    L.mg_cnn_set_state.restype = C.c_int
+    L.mg_cnn_set_state.argtypes = [vp, vp, vp, vp, C.c_int32]
     L.mg_cnn_gradient_trace.restype = C.c_int
     L.mg_cnn_gradient_trace.argtypes = [vp, cvp, cvp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
     L.mg_cnn_activation.restype = C.c_int
@@ -686,6 +690,22 @@ class WarmStartCNN:
         p = np.empty(self.n_params, dtype=np.float32)
         _ccheck(lib.mg_cnn_get_params(self.c, p.ctypes.data), self.c)
         return p
+
+    def get_state(self) -> dict:
+        """Training checkpoint: parameters, Adam moments m and v (float32 numpy) and the step count."""
+        import numpy as np
+        w, m, v = (np.empty(self.n_params, dtype=np.float32) for _ in range(3))
+        step = C.c_int32()
+        _ccheck(lib.mg_cnn_get_state(self.c, w.ctypes.data, m.ctypes.data, v.ctypes.data, C.byref(step)), self.c)
+        return {"params": w, "m": m, "v": v, "step": int(step.value)}
+
+    def set_state(self, state: dict) -> None:
+        import numpy as np
+        arrs = [np.ascontiguousarray(np.asarray(state[k], dtype=np.float32)) for k in ("params", "m", "v")]
+        if any(a.size != self.n_params for a in arrs):
+            raise ValueError(f"expected {self.n_params} values per array")
+        _ccheck(lib.mg_cnn_set_state(self.c, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                                     int(state["step"])), self.c)
 
     @staticmethod
     def _img(t: torch.Tensor, name: str):

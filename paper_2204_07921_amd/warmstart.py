@@ -163,9 +163,77 @@ def evaluate(net: mgcurv.WarmStartCNN, f: torch.Tensor, rel_tol: float = 1e-6, b
                                       "energy_gap_rel_mean": float(np.mean((e_tol - e_plain) / e_plain))}}
 
 
+def evaluate_single(net: mgcurv.WarmStartCNN, f: torch.Tensor, fine_colours: int = 9, rel_tol: float = 1e-6,
+                    budget_factor: float = 3.0, max_vcycles: int = 2000) -> dict:
+    """The same comparison image by image on the single-image solver, which also runs the nine-colour
+    pixel level (the batched path runs four colours only).  Per image: the plain solve from u0 = f to
+    the relative energy change rel_tol gives F_plain; the warm start (CNN forward, then V-cycles until
+    F <= F_plain (1 + 1e-6), within budget_factor x the plain V-cycles, else the plain solve as
+    fallback, its time added) is timed CNN included."""
+    n, h, w = f.shape
+    s = mgcurv.Solver(h, w, alpha=ALPHA, kind=KIND, dtype=torch.float32, fine_colours=fine_colours)
+    u = f[0].clone()
+    s.vcycle(u, f[0].contiguous())   # warm-up
+    forward_chunked(net, f[:1].contiguous())
+    rows = []
+    for k in range(n):
+        fk = f[k].contiguous()
+        u = fk.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rp = s.solve(u, fk, rel_tol=rel_tol, max_vcycles=max_vcycles)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t
+        t = time.perf_counter()
+        u0 = forward_chunked(net, f[k:k + 1].contiguous())[0]
+        torch.cuda.synchronize()
+        t_cnn = time.perf_counter() - t
+        e_cnn = s.energy(u0, fk)
+        t = time.perf_counter()
+        rw = s.solve_target(u0, fk, rp["energy"] * (1 + 1e-6), max_vcycles=int(budget_factor * rp["vcycles"]) + 1)
+        torch.cuda.synchronize()
+        t_warm = t_cnn + time.perf_counter() - t
+        fallback = rw["status"] != 0
+        if fallback:
+            uu = fk.clone()
+            t = time.perf_counter()
+            s.solve(uu, fk, rel_tol=rel_tol, max_vcycles=max_vcycles)
+            torch.cuda.synchronize()
+            t_warm += time.perf_counter() - t
+        rows.append({"plain_vcycles": rp["vcycles"], "plain_status": rp["status"], "plain_energy": rp["energy"],
+                     "plain_seconds": t_plain, "cnn_energy": e_cnn, "warm_vcycles": rw["vcycles"],
+                     "warm_energy": rw["energy"], "warm_seconds": t_warm, "fallback": fallback})
+    s.close()
+    tp = sum(r["plain_seconds"] for r in rows)
+    tw = sum(r["warm_seconds"] for r in rows)
+    return {"images": n, "size": [h, w], "fine_colours": fine_colours,
+            "plain": {"seconds": round(tp, 4), "vcycles_mean": float(np.mean([r["plain_vcycles"] for r in rows])),
+                      "converged": int(sum(r["plain_status"] == 0 for r in rows))},
+            "cnn_above_plain_energy": int(sum(r["cnn_energy"] > r["plain_energy"] for r in rows)),
+            "warm": {"seconds": round(tw, 4), "vcycles_mean": float(np.mean([r["warm_vcycles"] for r in rows])),
+                     "vcycles_min": int(min(r["warm_vcycles"] for r in rows)),
+                     "vcycles_max": int(max(r["warm_vcycles"] for r in rows)),
+                     "fallbacks": int(sum(r["fallback"] for r in rows))},
+            "final_energy_gap_rel_max": float(max((r["warm_energy"] - r["plain_energy"]) / r["plain_energy"] for r in rows)),
+            "speedup": round(tp / max(tw, 1e-9), 3), "per_image": rows}
+
+
 def save(path: str, params: np.ndarray, meta: dict):
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     np.savez(path, params=np.asarray(params, dtype=np.float32), meta=json.dumps(meta))
+
+
+def save_checkpoint(path: str, state: dict, meta: dict | None = None):
+    """Training checkpoint (parameters, Adam moments and step) as a plain .npz (no pickled objects)."""
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, params=np.asarray(state["params"], dtype=np.float32), m=np.asarray(state["m"], dtype=np.float32),
+             v=np.asarray(state["v"], dtype=np.float32), step=np.int64(state["step"]), meta=json.dumps(meta or {}))
+
+
+def load_checkpoint(path: str) -> dict:
+    with np.load(path, allow_pickle=False) as z:
+        return {"params": z["params"].astype(np.float32), "m": z["m"].astype(np.float32),
+                "v": z["v"].astype(np.float32), "step": int(z["step"]), "meta": json.loads(str(z["meta"]))}
 
 
 def load(path: str = DEFAULT_WEIGHTS):
