@@ -232,8 +232,17 @@ def batch_measure(steps: int, solve: bool) -> dict:
     bs.solve(ud, fd, rel_tol=0.0, max_vcycles=steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    # algorithmic FP64 work of one V-cycle of the batch: per image, level by level, ring pixels per image
+    # pixel (9 at b = 1, 8 / b above) x 51 evaluations x 40 (mean) or 30 (Gaussian) flops per ring pixel
+    flops = 0.0
+    for sp in specs:
+        levels = max(1, int(np.ceil(np.log2(max(sp["height"], sp["width"])))))
+        ring_per_px = 9.0 + sum(8.0 / (1 << (j - 1)) for j in range(2, levels + 1))
+        flops += sp["height"] * sp["width"] * ring_per_px * 51 * (40 if sp["kind"] == 0 else 30)
+    tflops = flops * steps / dt / 1e12
     out = {"workload": f"256 mixed images, {mpx:.1f} Mpixel, mean and Gaussian curvature, alpha 10/20/40",
            "value": round(mpx * steps / dt, 3), "unit": "Mpixel*V-cycles/s", "ms_per_vcycle": round(dt / steps * 1e3, 3),
+           "algorithmic_tflops": round(tflops, 2), "fp64_frac": round(tflops / FP64_PEAK_TFLOPS, 4),
            "tune_seconds": round(tune_s, 2),
            "tuned": {str(l): bs.config(l) for l in range(1, bs.levels + 1)}}
     if solve:
