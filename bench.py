@@ -93,6 +93,8 @@ def parse():
                     help="skip the paper's 2^j - 1 block schedule measurement")
     ap.add_argument("--recon-only", action="store_true",
                     help="run only the reconstruction measurement and print its JSON (for profiling its kernels)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 256-image batched measurement and print its JSON (for profiling its kernels)")
     ap.add_argument("--fbs-only", action="store_true",
                     help="run only the FBS measurement and print its JSON (for profiling its kernels)")
     ap.add_argument("--warm-batch", type=int, default=64,
@@ -604,6 +606,9 @@ def main():
         return
     if args.recon_only:
         print(json.dumps({"recon": recon_measure(args.steps, args.warmup)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_measure(args.batch_steps, args.batch_solve)}), flush=True)
         return
     if args.study:
         fn = {"cycle": lambda: study_cycle(args.kind), "fbs": lambda: study_fbs(args.kind)}[args.study]
