@@ -33,7 +33,9 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int C = 32;          // hidden channels
 constexpr int NL = 6;          // layers
-constexpr int TH = 8, TW = 32; // output tile of the 32 -> 32 kernels (rows x cols)
+constexpr int TH = 8, TW = 32; // pixel tile of the 32 -> 32 weight gradient (rows x cols)
+constexpr int CTH = 8;         // rows of the 32 -> 32 convolution's output tile (CTH x TW)
+constexpr int RPW = CTH / 4;   // tile rows per wavefront (four wavefronts)
 constexpr int PXS = 40;        // LDS pixel stride in bf16 (80 bytes: 8 lanes cover all banks)
 
 // parameter offsets in the flat vector (W_l (3,3,ci,co) row-major, then b_l)
@@ -61,8 +63,8 @@ __device__ __forceinline__ float from_bf16(bf16 x)
 
 // ---------------------------------------------------------------------------
 // 32 -> 32 convolution on MFMA.  One workgroup (4 wavefronts) computes an
-// 8 x 32 pixel tile for all 32 output channels; wave w owns rows 2w, 2w+1,
-// i.e. four 16-pixel M tiles, times two 16-channel N tiles.
+// CTH x 32 pixel tile for all 32 output channels; wave w owns the RPW = CTH/4
+// rows from RPW*w, i.e. 2*RPW 16-pixel M tiles, times two 16-channel N tiles.
 //   y[p][o] = sum_tap sum_i x[p + off(tap)][i] * Wt[tap][o][i]   (zero outside the image)
 // FWD:   y = relu(acc + bias)               (Wt[tap][o][i] = W[ky][kx][i][o])
 // DGRAD: y = acc * (mask[p][o] > 0)         (Wt[tap'][o][i] = W[2-ky][2-kx][o][i], x = dz of the next layer)
@@ -72,17 +74,17 @@ __global__ __launch_bounds__(256) void conv32_kernel(const bf16* __restrict__ x,
                                                      const bf16* __restrict__ Wt, const float* __restrict__ bias,
                                                      const bf16* __restrict__ mask, int N, int H, int W)
 {
-    __shared__ __attribute__((aligned(16))) bf16 xs[(TH + 2) * (TW + 2) * PXS];
-    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    __shared__ __attribute__((aligned(16))) bf16 xs[(CTH + 2) * (TW + 2) * PXS];
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + CTH - 1) / CTH;
     const int tile = blockIdx.x;
     const int n = tile / (tiles_x * tiles_y);
     const int trem = tile - n * tiles_x * tiles_y;
     const int ty = trem / tiles_x, tx = trem - ty * tiles_x;
-    const int r0 = ty * TH, c0 = tx * TW;
+    const int r0 = ty * CTH, c0 = tx * TW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     // stage the input tile with a one-pixel halo (zeros outside the image)
-    for (int q = tid; q < (TH + 2) * (TW + 2) * 4; q += 256) {
+    for (int q = tid; q < (CTH + 2) * (TW + 2) * 4; q += 256) {
         const int pix = q >> 2, part = q & 3;
         const int rr = pix / (TW + 2), cc = pix - rr * (TW + 2);
         const int gi = r0 - 1 + rr, gj = c0 - 1 + cc;
@@ -100,17 +102,17 @@ __global__ __launch_bounds__(256) void conv32_kernel(const bf16* __restrict__ x,
             wb[tap][nt] = *reinterpret_cast<const bf16x8*>(Wt + ((size_t)tap * C + nt * 16 + (lane & 15)) * C + 8 * (lane >> 4));
     __syncthreads();
 
-    floatx4 acc[4][2];
+    floatx4 acc[2 * RPW][2];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < 2 * RPW; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int rr = 2 * wave + (mt >> 1) + dy;         // halo-tile row
+        for (int mt = 0; mt < 2 * RPW; ++mt) {
+            const int rr = RPW * wave + (mt >> 1) + dy;       // halo-tile row
             const int cc = (mt & 1) * 16 + (lane & 15) + dx;   // halo-tile column
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + (rr * (TW + 2) + cc) * PXS + 8 * (lane >> 4));
 #pragma unroll
@@ -121,12 +123,12 @@ __global__ __launch_bounds__(256) void conv32_kernel(const bf16* __restrict__ x,
     __syncthreads();  // xs is reused as the output staging tile
     // lane holds D[4*(lane/16) + i][lane%16] of each (mt, nt): pixel, channel
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < 2 * RPW; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int prow = 2 * wave + (mt >> 1);
+                const int prow = RPW * wave + (mt >> 1);
                 const int pcol = (mt & 1) * 16 + 4 * (lane >> 4) + i;
                 const int ch = nt * 16 + (lane & 15);
                 float v = acc[mt][nt][i];
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(256) void conv32_kernel(const bf16* __restrict__ x,
                 xs[(prow * TW + pcol) * PXS + ch] = to_bf16(v);
             }
     __syncthreads();
-    for (int q = tid; q < TH * TW * 4; q += 256) {
+    for (int q = tid; q < CTH * TW * 4; q += 256) {
         const int pix = q >> 2, part = q & 3;
         const int rr = pix / TW, cc = pix - rr * TW;
         const int gi = r0 + rr, gj = c0 + cc;
@@ -632,7 +634,7 @@ mg_status forward(mg_cnn* c, const float* f, float* u, const float* target, int 
     const size_t total = (size_t)n * H * W;
     hipLaunchKernelGGL(conv_in_kernel, dim3(grid_for(total)), dim3(256), 0, c->stream, f, c->act[0], c->W0q,
                        c->w + boff(0), n, H, W);
-    const int tiles = n * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+    const int tiles = n * ((H + CTH - 1) / CTH) * ((W + TW - 1) / TW);
     for (int l = 1; l <= 4; ++l)
         hipLaunchKernelGGL(conv32_kernel<false>, dim3(tiles), dim3(256), 0, c->stream, c->act[l - 1], c->act[l],
                            c->Wf + (size_t)(l - 1) * 9 * C * C, c->w + boff(l), (const bf16*)nullptr, n, H, W);
@@ -650,7 +652,8 @@ mg_status backward(mg_cnn* c, const float* f, int n, int H, int W, void* trace_d
 {
     const size_t total = (size_t)n * H * W;
     hipError_t e;
-    const int tiles = n * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+    const int tiles = n * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);      // weight-gradient tiles
+    const int ctiles = n * ((H + CTH - 1) / CTH) * ((W + TW - 1) / TW);   // convolution tiles
     // output layer: weight gradient partials and dz4
     const int stiles = n * ((H + SW_TH - 1) / SW_TH) * ((W + SW_TW - 1) / SW_TW);
     const int nb_small = stiles < SW_WG ? stiles : SW_WG;
@@ -676,7 +679,7 @@ mg_status backward(mg_cnn* c, const float* f, int n, int H, int W, void* trace_d
         hipLaunchKernelGGL(wgrad32_kernel, dim3(nwg), dim3(256), 0, c->stream, c->act[l - 1], dz, c->part, n, H, W);
         sum_partials(c, c->part, nwg, 9 * C * C + C, 9 * C * C + C, c->g + woff(l));
         // input gradient through layer l, masked by a_l > 0 (the ReLU of layer l - 1)
-        hipLaunchKernelGGL(conv32_kernel<true>, dim3(tiles), dim3(256), 0, c->stream, dz, other,
+        hipLaunchKernelGGL(conv32_kernel<true>, dim3(ctiles), dim3(256), 0, c->stream, dz, other,
                            c->Wb + (size_t)(l - 1) * 9 * C * C, (const float*)nullptr, c->act[l - 1], n, H, W);
         if ((e = trace(other, l - 1)) != hipSuccess) return chip(c, e, "trace copy");
         bf16* t = dz; dz = other; other = t;
