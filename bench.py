@@ -97,6 +97,8 @@ def parse():
                     help="run only the 256-image batched measurement and print its JSON (for profiling its kernels)")
     ap.add_argument("--fbs-only", action="store_true",
                     help="run only the FBS measurement and print its JSON (for profiling its kernels)")
+    ap.add_argument("--fbs-size", type=int, default=1024,
+                    help="image side of --fbs-only; other than 1024 only the V-cycle rate is measured")
     ap.add_argument("--warm-batch", type=int, default=64,
                     help="also compare plain and warm-started batched solves on this many 1024x1024 images")
     return ap.parse_args()
@@ -270,7 +272,7 @@ def batch_measure(steps: int, solve: bool) -> dict:
     return out
 
 
-def fbs_measure(steps: int, warmup: int) -> dict:
+def fbs_measure(steps: int, warmup: int, n: int = H) -> dict:
     """The paper's own local step (one FBS update per patch with tangent-plane estimates, patches
     of side 2^j - 1, J = 3) in the paper's intensity regime: the same kind of synthetic image
     scaled to [0, 255] with noise sigma 0.08 * 255, alpha 0.05.  Graph-replayed V-cycles per second
@@ -279,16 +281,16 @@ def fbs_measure(steps: int, warmup: int) -> dict:
     import torch
     from paper_2204_07921_amd import mgcurv
     from synth import noisy_image
-    f32, g = noisy_image(H, W, SEED, 0.08, dtype=np.float32)
+    f32, g = noisy_image(n, n, SEED, 0.08, dtype=np.float32)
     f32 = (255.0 * f32).astype(np.float32)
     g = 255.0 * g.astype(np.float64)
     fd = torch.tensor(f32, device="cuda")
     rmse = lambda u: float(np.sqrt(np.mean((u.detach().cpu().numpy().astype(np.float64) - g) ** 2)))
-    out = {"workload": "1024x1024 synthetic image scaled to [0, 255], noise sigma 0.08 * 255, alpha 0.05, "
+    out = {"workload": f"{n}x{n} synthetic image scaled to [0, 255], noise sigma 0.08 * 255, alpha 0.05, "
                        "J = 3 (patch sides 1, 3, 7), one FBS step per patch, float32 state, FP64 updates",
            "noise_rmse": round(rmse(fd), 4)}
     for kind, name in ((0, "mean"), (1, "gaussian")):
-        s = mgcurv.FbsSolver(H, W, alpha=0.05, kind=kind, levels=3, dtype=torch.float32)
+        s = mgcurv.FbsSolver(n, n, alpha=0.05, kind=kind, levels=3, dtype=torch.float32)
         u = fd.clone()
         for _ in range(warmup):
             s.vcycle(u, fd)
@@ -298,6 +300,11 @@ def fbs_measure(steps: int, warmup: int) -> dict:
             s.vcycle(u, fd)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
+        if n != H:
+            out[name] = {"value": round(n * n / dt / 1e6, 3), "unit": "Mpixel*V-cycles/s",
+                         "ms_per_vcycle": round(dt * 1e3, 4)}
+            s.close()
+            continue
         u = fd.clone()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -307,7 +314,7 @@ def fbs_measure(steps: int, warmup: int) -> dict:
         ex = mgcurv.Solver(H, W, alpha=0.05, kind=kind, dtype=torch.float32)
         ue = fd.clone()
         rex = ex.solve(ue, fd, rel_tol=1e-6, max_vcycles=300)
-        out[name] = {"value": round(H * W / dt / 1e6, 3), "unit": "Mpixel*V-cycles/s", "ms_per_vcycle": round(dt * 1e3, 4),
+        out[name] = {"value": round(n * n / dt / 1e6, 3), "unit": "Mpixel*V-cycles/s", "ms_per_vcycle": round(dt * 1e3, 4),
                      "solve_relerr_1e-4": {"seconds": round(el, 4), "vcycles": res["vcycles"], "status": res["status"],
                                            "energy": res["energy"], "rmse": round(rmse(u), 4)},
                      "exact_local_minimisation_1e-6": {"vcycles": rex["vcycles"], "energy": rex["energy"],
@@ -612,7 +619,7 @@ def main():
                           "sharding)", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.fbs_only:
-        print(json.dumps({"fbs": fbs_measure(args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"fbs": fbs_measure(args.steps, args.warmup, args.fbs_size)}), flush=True)
         return
     if args.recon_only:
         print(json.dumps({"recon": recon_measure(args.steps, args.warmup)}), flush=True)

@@ -18,11 +18,12 @@
 //
 // Data flow per V-cycle (state dtype T = float or double, local math in FP64):
 //   level 1 (b = 1): one launch; a workgroup loads a 64 x 64 tile (32 x 64 for
-//     double) of u and f with a 4-pixel halo into LDS and runs the four colour
-//     sweeps there, shrinking the
-//     region it trusts by one pixel per colour (each sweep reads one pixel
-//     around the updated pixel), then writes the tile to the other buffer.
-//     Every pixel is read once and written once per level.
+//     double) of u with a 4-pixel halo into LDS (16-byte vectors when the box
+//     lies inside the image) and runs the four colour sweeps there, shrinking
+//     the region it trusts by one pixel per colour (each sweep reads one pixel
+//     around the updated pixel) and reading f at the pixels it solves, then
+//     writes the tile to the other buffer.  Every pixel is read once and
+//     written once per level.
 //   levels with patch side 3 and 7: one launch each, the same scheme with a
 //     tile of patches and a halo of 4 patches (corrections kept in LDS); the
 //     sums of f over their patches come from one pass over f per V-cycle.
@@ -76,7 +77,28 @@ __device__ __forceinline__ double pixel_correction(const At& at, int i, int j, i
         ring_accumulate<KIND>(uo + c, w8, 1.0, 0, sum, g);
         const double est = KIND == 0 ? sum * 0.125 : gc_choice(g);
         c = backward(c, c + est, eta * alpha, fs);
-        eta = 1.0 / sqrt(1.0 + (double)t);
+        if (t + 1 < steps) eta = 1.0 / sqrt(1.0 + (double)t);
+    }
+    return c;
+}
+
+// The same correction for a pixel off the image border: no tap is clamped, so
+// none is the pixel itself, and the eight ring values are read from LDS at fixed
+// offsets of the centre (W, E, N, S, NW, SE, NE, SW for a row stride LW).
+template <int KIND, int LW, typename T>
+__device__ __forceinline__ double interior_correction(const T* __restrict__ cp, double uo, double fs, double alpha,
+                                                      int steps)
+{
+    const double v[8] = {(double)cp[-1],      (double)cp[1],      (double)cp[-LW],     (double)cp[LW],
+                         (double)cp[-LW - 1], (double)cp[LW + 1], (double)cp[-LW + 1], (double)cp[LW - 1]};
+    double c = 0.0, eta = 1.0;
+    for (int t = 0; t < steps; ++t) {
+        double sum = 0.0;
+        GcAcc g = gc_empty();
+        ring_accumulate<KIND>(uo + c, v, 1.0, 0, sum, g);
+        const double est = KIND == 0 ? sum * 0.125 : gc_choice(g);
+        c = backward(c, c + est, eta * alpha, fs);
+        if (t + 1 < steps) eta = 1.0 / sqrt(1.0 + (double)t);
     }
     return c;
 }
@@ -84,19 +106,28 @@ __device__ __forceinline__ double pixel_correction(const At& at, int i, int j, i
 template <typename T, int KIND, int TH, int TW, int NT>
 __global__ __launch_bounds__(NT) void fbs_pixel_level_kernel(const T* __restrict__ uin, T* __restrict__ uout,
                                                              const T* __restrict__ f, int H, int W, double alpha,
-                                                             int steps)
+                                                             int steps, int vec16)
 {
     constexpr int LW = TW + 2 * PHALO;
-    __shared__ T su[(TH + 2 * PHALO) * LW];
-    __shared__ T sf[(TH + 2 * PHALO) * LW];
+    __shared__ __attribute__((aligned(16))) T su[(TH + 2 * PHALO) * LW];
     const int y0 = blockIdx.y * TH, x0 = blockIdx.x * TW;
     const int ly = y0 - PHALO, lx = x0 - PHALO;
     const int r_lo = max(0, ly), r_hi = min(H, y0 + TH + PHALO);
     const int c_lo = max(0, lx), c_hi = min(W, x0 + TW + PHALO);
     const int nr = r_hi - r_lo, nc = c_hi - c_lo;
-    // u and f of the loaded region (f is read by the pixels solved, all inside it)
-    tile_copy<NT, 12>(nr, nc, uin + (size_t)r_lo * W + c_lo, (long)W, su + (r_lo - ly) * LW + (c_lo - lx), LW);
-    tile_copy<NT, 12>(nr, nc, f + (size_t)r_lo * W + c_lo, (long)W, sf + (r_lo - ly) * LW + (c_lo - lx), LW);
+    // a tile whose loaded box lies inside the image moves whole 16-byte vectors (vec16: the
+    // buffers and the row length allow it); the others take the general copy
+    const bool box = vec16 && ly >= 0 && lx >= 0 && y0 + TH + PHALO <= H && x0 + TW + PHALO <= W;
+    // with a margin on every side (no loaded edge is an image edge) every pixel the tile solves
+    // lies off the image border, at least one pixel inside the loaded box: the whole workgroup
+    // takes the unclamped form
+    const bool inner = ly > 0 && lx > 0 && y0 + TH + PHALO < H && x0 + TW + PHALO < W;
+    // u of the loaded region; f is read from memory at the pixel solved (once per colour that
+    // solves it), which halves the workgroup's LDS and lets more workgroups share a CU
+    if (box)
+        box_copy16<NT, TH + 2 * PHALO, LW>(uin + (size_t)ly * W + lx, (long)W, su, LW);
+    else
+        tile_copy<NT, 12>(nr, nc, uin + (size_t)r_lo * W + c_lo, (long)W, su + (r_lo - ly) * LW + (c_lo - lx), LW);
     __syncthreads();
     auto at = [&](int ii, int jj) { return (double)su[(ii - ly) * LW + (jj - lx)]; };
     for (int k = 0; k < 4; ++k) {
@@ -108,16 +139,22 @@ __global__ __launch_bounds__(NT) void fbs_pixel_level_kernel(const T* __restrict
         if (ni > 0 && nj > 0)
         for (GridWalk w(threadIdx.x, NT, nj); w.a < ni; w.next()) {
             const int i = i0 + 2 * w.a, j = j0 + 2 * w.b;
-            const double uo = at(i, j);
-            const double fs = (double)sf[(i - ly) * LW + (j - lx)] - uo;
-            const double c = pixel_correction<KIND>(at, i, j, H, W, fs, alpha, steps);
+            const int o = (i - ly) * LW + (j - lx);
+            const double fv = (double)f[(size_t)i * W + j];
+            const double uo = (double)su[o];
+            const double fs = fv - uo;
+            const double c = inner ? interior_correction<KIND, LW>(su + o, uo, fs, alpha, steps)
+                                   : pixel_correction<KIND>(at, i, j, H, W, fs, alpha, steps);
             // pixels of one colour read only other colours (or themselves), so the write is safe
-            su[(i - ly) * LW + (j - lx)] = (T)(uo + c);
+            su[o] = (T)(uo + c);
         }
         __syncthreads();
     }
     const int onr = min(H, y0 + TH) - y0, onc = min(W, x0 + TW) - x0;
-    tile_copy<NT, 8>(onr, onc, su + (y0 - ly) * LW + (x0 - lx), LW, uout + (size_t)y0 * W + x0, (long)W);
+    if (box)
+        box_copy16<NT, TH, TW>(su + PHALO * LW + PHALO, LW, uout + (size_t)y0 * W + x0, (long)W);
+    else
+        tile_copy<NT, 8>(onr, onc, su + (y0 - ly) * LW + (x0 - lx), LW, uout + (size_t)y0 * W + x0, (long)W);
 }
 
 // Tile of the pixel level per state type: (rows, columns, threads).
@@ -573,12 +610,14 @@ hipError_t launch_pixel_level(const mg_fbs_ctx* c, hipStream_t st, const void* u
     const int H = c->P.height, W = c->P.width;
     using Tile = fbs::PixelTile<T>;
     dim3 grid((W + Tile::TW - 1) / Tile::TW, (H + Tile::TH - 1) / Tile::TH), block(Tile::NT);
+    // 16-byte accesses need 16-byte aligned buffers and rows of whole vectors
+    const int vec16 = ((((uintptr_t)uin | (uintptr_t)uout | (uintptr_t)f) & 15) == 0) && W % (16 / (int)sizeof(T)) == 0;
     if (c->P.curvature == MG_CURV_MEAN)
         hipLaunchKernelGGL((fbs::fbs_pixel_level_kernel<T, 0, Tile::TH, Tile::TW, Tile::NT>), grid, block, 0, st,
-                           (const T*)uin, (T*)uout, (const T*)f, H, W, c->P.alpha, c->P.steps);
+                           (const T*)uin, (T*)uout, (const T*)f, H, W, c->P.alpha, c->P.steps, vec16);
     else
         hipLaunchKernelGGL((fbs::fbs_pixel_level_kernel<T, 1, Tile::TH, Tile::TW, Tile::NT>), grid, block, 0, st,
-                           (const T*)uin, (T*)uout, (const T*)f, H, W, c->P.alpha, c->P.steps);
+                           (const T*)uin, (T*)uout, (const T*)f, H, W, c->P.alpha, c->P.steps, vec16);
     return hipGetLastError();
 }
 

@@ -194,4 +194,32 @@ __device__ __forceinline__ void tile_copy(int nr, int nc, const T* __restrict__ 
     }
 }
 
+// dst[r * dstride + c] = src[r * sstride + c] for an NR x NC box in 16-byte
+// accesses (src, dst and both strides 16-byte aligned, NC whole vectors); each
+// thread issues all of its loads before its stores.  Loads past the box read its
+// last vector again, so none is conditional and all stay in registers (a
+// conditionally loaded vector array is kept in scratch memory, one load at a
+// time); only the stores are guarded.
+template <int NT, int NR, int NC, class T, class SS, class DS>
+__device__ __forceinline__ void box_copy16(const T* __restrict__ src, SS sstride, T* __restrict__ dst, DS dstride)
+{
+    constexpr int V = 16 / (int)sizeof(T), NV = NC / V, N = NR * NV, K = (N + NT - 1) / NT;
+    static_assert(NC % V == 0, "rows must be whole 16-byte vectors");
+    uint4 x[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const int q = min((int)threadIdx.x + m * NT, N - 1);
+        const int r = q / NV, cv = q - r * NV;
+        x[m] = *reinterpret_cast<const uint4*>(src + (SS)r * sstride + cv * V);
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const int q = (int)threadIdx.x + m * NT;
+        if (q < N) {
+            const int r = q / NV, cv = q - r * NV;
+            *reinterpret_cast<uint4*>(dst + (DS)r * dstride + cv * V) = x[m];
+        }
+    }
+}
+
 }  // namespace fbs

@@ -109,6 +109,32 @@ def test_levels_match_oracle(mg, dtype, kind, shape):
         _compare(host(ud), ref, scale, dtype, f"level {level}")
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("w,offset,steps", [(260, 0, 1), (260, 0, 3), (262, 0, 2), (263, 0, 1), (260, 1, 1)])
+def test_pixel_level_tile_copies(mg, dtype, kind, w, offset, steps):
+    """The fused pixel level on 300 x w images whose middle tiles lie inside the image: rows of
+    whole 16-byte vectors and aligned buffers (the vector copies), odd and 2-mod-4 row lengths and
+    buffers one element off alignment (the general copy), one to three FBS updates per pixel."""
+    h = 300
+    alpha, scale = REGIMES[1]
+    f, u0 = _inputs(h, w, 31, scale, dtype, perturb=0.03)
+    o = FbsOracle(h, w, alpha, kind, levels=2, steps=steps, round_f32=dtype == torch.float32)
+    s = mg.FbsSolver(h, w, alpha, kind, levels=2, dtype=dtype, steps=steps)
+    _case(f"fbs pixel level {h}x{w} kind={kind} {dtype} offset={offset} steps={steps}")
+    ref = u0.copy()
+    o.level(ref, f, 1)
+    n = h * w
+    ubuf = torch.zeros(n + offset, dtype=dtype, device="cuda")
+    fbuf = torch.zeros(n + offset, dtype=dtype, device="cuda")
+    ud, fd = ubuf[offset:].view(h, w), fbuf[offset:].view(h, w)
+    ud.copy_(dev(u0, dtype))
+    fd.copy_(dev(f, dtype))
+    s.level(ud, fd, 1)
+    _compare(host(ud), ref, scale, dtype, "pixel level")
+    assert not np.array_equal(ref, u0)
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("cycle,steps,J", [(0, 1, 3), (1, 1, 3), (0, 15, 3), (0, 1, 7)])
 def test_vcycles_free_running(mg, kind, cycle, steps, J):
