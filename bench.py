@@ -77,7 +77,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the 4096^2 and 8192^2 per-level leg")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the 4096^2 / 8192^2 leg and print its JSON (for profiling its kernels)")
-    ap.add_argument("--large-sizes", default="4096,8192")
+    ap.add_argument("--large-sizes", default="4096,8192,1024x8192",
+                    help="sides (N) or rows x columns (HxW); 1024x8192 is one GPU's row slab of 8192x8192 over 8 GPUs")
     ap.add_argument("--study", choices=["cycle", "fbs"],
                     help="run one study instead of the benchmark and print its JSON: 'cycle' = J x cycle shape x "
                          "block schedule of the exact path at 1024x1024, 'fbs' = the same for the paper's FBS step "
@@ -484,20 +485,37 @@ def cpu_baseline(f64: np.ndarray, kind: int, vcycles: int, u_gpu: np.ndarray, e_
     return base, err
 
 
+def parse_sizes(text: str):
+    """'4096,8192,1024x8192' -> [(4096, 4096), (8192, 8192), (1024, 8192)] (rows x columns)."""
+    out = []
+    for tok in text.split(","):
+        tok = tok.strip().lower()
+        if not tok:
+            continue
+        if "x" in tok:
+            h, w = tok.split("x")
+            out.append((int(h), int(w)))
+        else:
+            out.append((int(tok), int(tok)))
+    return out
+
+
 def large_measure(sizes, stream) -> dict:
     """4096x4096 (J = 12) and 8192x8192 (J = 13), sigma 0.1, float state, mean and Gaussian curvature:
     V-cycles per second and each level's time (HIP events on the library's stream), with the
-    algorithmic HBM rate of each level against the 8 TB/s peak."""
+    algorithmic HBM rate of each level against the 8 TB/s peak.  A rows x columns entry such as
+    1024x8192 is one GPU's row slab of the 8192x8192 image split over 8 GPUs: its levels with
+    blocks inside the slab are compared with the full image's same levels divided by 8."""
     import torch
     from paper_2204_07921_amd import mgcurv
     from synth import noisy_image
     out = {}
-    for n in sizes:
-        f32, _ = noisy_image(n, n, SEED, SIGMA, dtype=np.float32)
+    for hn, wn in sizes:
+        f32, _ = noisy_image(hn, wn, SEED, SIGMA, dtype=np.float32)
         fd = torch.tensor(f32, device="cuda")
         del f32
         for kind in (0, 1):
-            s = mgcurv.Solver(n, n, alpha=ALPHA, kind=kind, dtype=torch.float32, stream=stream)
+            s = mgcurv.Solver(hn, wn, alpha=ALPHA, kind=kind, dtype=torch.float32, stream=stream)
             u = fd.clone()
             s.vcycle(u, fd)
             torch.cuda.synchronize()
@@ -518,10 +536,10 @@ def large_measure(sizes, stream) -> dict:
                 side = 1 << (level - 1)
                 bpp = BYTES_PER_PX_LEVEL_FINE if side < 32 else BYTES_PER_PX_LEVEL_COARSE
                 level_ms.append(round(ms, 4))
-                level_gbs.append(round(bpp * n * n / (ms * 1e-3) / 1e9, 1))
+                level_gbs.append(round(bpp * hn * wn / (ms * 1e-3) / 1e9, 1))
             e = s.energy(u, fd)
-            out[f"{n}x{n}_{'mean' if kind == 0 else 'gaussian'}"] = {
-                "levels": s.levels, "value": round(n * n / dt / 1e6, 3), "unit": "Mpixel*V-cycles/s",
+            out[f"{hn}x{wn}_{'mean' if kind == 0 else 'gaussian'}"] = {
+                "levels": s.levels, "value": round(hn * wn / dt / 1e6, 3), "unit": "Mpixel*V-cycles/s",
                 "ms_per_vcycle": round(dt * 1e3, 3), "level_ms": level_ms,
                 "level_algorithmic_gbs": level_gbs,
                 "level_hbm_frac": [round(g / HBM_PEAK_GBS, 4) for g in level_gbs],
@@ -530,6 +548,22 @@ def large_measure(sizes, stream) -> dict:
             del u
         del fd
         torch.cuda.empty_cache()
+    # row slabs: the levels whose blocks stay inside the slab (side <= half its height) against the
+    # full image's same levels over the number of slabs
+    for (hn, wn) in sizes:
+        full = (wn, wn)
+        if hn >= wn or full not in sizes or wn % hn:
+            continue
+        parts = wn // hn
+        local = max(1, (hn // 2).bit_length())   # levels 1 .. log2(hn / 2) + 1
+        for kind in ("mean", "gaussian"):
+            slab, whole = out[f"{hn}x{wn}_{kind}"], out[f"{wn}x{wn}_{kind}"]
+            t_slab = sum(slab["level_ms"][:local])
+            t_share = sum(whole["level_ms"][:local]) / parts
+            out[f"{hn}x{wn}_{kind}"]["slab_of"] = {
+                "image": f"{wn}x{wn}", "gpus": parts, "local_levels": local,
+                "slab_ms_local_levels": round(t_slab, 4), "full_image_ms_same_levels_per_gpu": round(t_share, 4),
+                "share_efficiency": round(t_share / t_slab, 3)}
     return out
 
 
@@ -633,8 +667,8 @@ def main():
         return
     if args.large_only:
         import torch
-        sizes = [int(x) for x in args.large_sizes.split(",") if x]
-        print(json.dumps({"large": large_measure(sizes, torch.cuda.current_stream())}), flush=True)
+        print(json.dumps({"large": large_measure(parse_sizes(args.large_sizes), torch.cuda.current_stream())}),
+              flush=True)
         return
     import torch
     from paper_2204_07921_amd import mgcurv
@@ -785,7 +819,7 @@ def main():
     if not args.no_recon:
         out["recon"] = recon_measure(5, 1)
     if not args.no_large:
-        out["large"] = large_measure([int(x) for x in args.large_sizes.split(",") if x], stream)
+        out["large"] = large_measure(parse_sizes(args.large_sizes), stream)
     if not args.no_cpu:
         out["cpu_baseline"], out["error_vs_fp64"] = cpu_baseline(f64, args.kind, args.cpu_vcycles, u1_host, e1,
                                                                  u1_64_host)

@@ -80,3 +80,9 @@ def test_cpu_threads_follow_the_process_share(monkeypatch):
     assert bench.cpu_threads() == min(3, len(os.sched_getaffinity(0)))
     monkeypatch.delenv("OMP_NUM_THREADS")
     assert bench.cpu_threads() == len(os.sched_getaffinity(0))
+
+
+def test_large_sizes_parse_squares_and_slabs():
+    import bench
+    assert bench.parse_sizes("4096, 8192,1024x8192") == [(4096, 4096), (8192, 8192), (1024, 8192)]
+    assert bench.parse_sizes("") == []
