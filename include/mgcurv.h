@@ -182,6 +182,25 @@ mg_status mg_curv_level(mg_curv_ctx *ctx, void *u, const void *f, int32_t level)
 /* Number of levels J the context uses (after resolving levels = 0). */
 int32_t mg_curv_levels(const mg_curv_ctx *ctx);
 
+/* Split solve of the coarse levels (the arg min of Algorithm 3, Section 2.2,
+ * computed by several workgroups per block).  Where a colour of a coarse
+ * level (block side 64..512) holds so few blocks that 2^d - 1 >= 7
+ * workgroups per block fit on the device's CUs, each block's samples are
+ * spread over its workgroups and its bisection takes d steps per exchange
+ * between them.  The corrections are bitwise those of the one-workgroup
+ * solve; only the time differs (a workgroup that waits too long for a value
+ * computes it itself, so results never depend on timing).  It is on by
+ * default when the context's levels have such colours (mg_curv_init then
+ * allocates the exchange words: 2 M + ceil(G / d)(2^d - 1) 64-bit words per
+ * block of the largest such launch, 32 KB or less at the default M and G).
+ * Launches under HIP stream capture use the one-workgroup solve.  enable: 1
+ * on (no effect if the context has no such level), 0 off.  Returns MG_OK,
+ * or MG_E_INVALID for a null context or another value. */
+mg_status mg_curv_set_split(mg_curv_ctx *ctx, int32_t enable);
+
+/* 1 if the context's coarse levels use the split solve, else 0 (also for NULL). */
+int32_t mg_curv_split_active(const mg_curv_ctx *ctx);
+
 /* Release the context (NULL is allowed).  Waits for its stream first. */
 void mg_curv_destroy(mg_curv_ctx *ctx);
 

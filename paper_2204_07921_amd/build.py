@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmgcurv.so")
 
-SOURCES = ["mgc_kernels.hip", "mgc_runtime.hip", "mgc_batch.hip", "mgc_cnn.hip", "mgc_fbs.hip", "mgc_recon.hip"]
+SOURCES = ["mgc_kernels.hip", "mgc_split.hip", "mgc_runtime.hip", "mgc_batch.hip", "mgc_cnn.hip", "mgc_fbs.hip", "mgc_recon.hip"]
 HEADERS = ["mgc_device.h", "mgc_internal.h", "mgc_sweep.h"]
 
 HIPCC_FLAGS = [

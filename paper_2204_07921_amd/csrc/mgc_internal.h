@@ -22,6 +22,21 @@ struct CoarseScratch {
     double* cpend_alt;  // the previous coarse level's, while they are applied by the next level's sums pass
     double* rec;        // expanded ring records of the streamed levels (shape side >= STREAMED_B)
     size_t rec_cap;     // doubles in rec
+    // split solve (one block on several workgroups, see mgc_split.hip); split_cus = 0: off
+    unsigned long long* xslots;   // xblocks regions of xstride exchange words
+    int xstride, xblocks;
+    unsigned xepoch;              // tag of the last split launch (0 is never a tag)
+    int split_cus;                // workgroups one launch may keep resident (the CU count)
+    int split_min_depth;          // split only when at least this many bisection steps share an exchange
+};
+
+// Exchange slots of one split launch: block k of the launch uses slots[k * stride ..];
+// P = 2^d - 1 workgroups per block; tag marks the words this launch writes.
+struct SplitArgs {
+    unsigned long long* slots;
+    int P, d;
+    int stride;
+    unsigned tag;
 };
 
 // Block side at level j (1-based): 2^(j-1) (schedule 0, nested blocks) or 2^j - 1
@@ -47,8 +62,17 @@ size_t record_scratch_doubles(int H, int W, int J, int schedule);
 
 // b = 1: colour sweep from uin into uout (every pixel of uout is written).
 hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours);
+// Tree depth d of the split solve for a launch of nblocks blocks of side b (0: not split):
+// the largest d <= min(8, G) with nblocks (2^d - 1) <= cus, for register-resident coarse sides >= 256.
+int split_depth(int nblocks, int cus, int G, int b);
+// Exchange words one block of a split launch needs: 2 M sample words and ceil(G / d) rounds of 2^d - 1.
+size_t split_slot_words(int M, int G, int d);
+// Coarse colour sweep of nbr x nbc blocks (colour (pr, pc)) by the split solve, P workgroups per block.
+struct CoarseArgs;
+hipError_t launch_sweep_split(const LaunchCtx& L, void* u, const void* f, int b, int pr, int pc, int nbr, int nbc,
+                              const CoarseArgs& ca, const SplitArgs& sa);
 // b >= 2: colour sweep (in place on fine levels, into cs.cpend on coarse levels).
-hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, const CoarseScratch& cs);
+hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, CoarseScratch& cs);
 // Coarse levels (level_is_lazy(b)): block sums and zeroed corrections before the
 // colours, the correction pass after them.
 bool level_is_lazy(int b);

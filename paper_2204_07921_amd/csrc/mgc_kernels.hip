@@ -313,7 +313,7 @@ size_t record_scratch_doubles(int H, int W, int J, int schedule)
     return need;
 }
 
-hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, const CoarseScratch& cs)
+hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b, int colour, CoarseScratch& cs)
 {
     const int pr = colour >> 1, pc = colour & 1;
     const int mj = (L.H + b - 1) / b, nj = (L.W + b - 1) / b;
@@ -321,6 +321,25 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
     CoarseArgs ca{cs.partials, cs.nchunk, cs.cpend, nj, nullptr, 8 * b};
     // streamed levels keep their expanded records in memory when the scratch holds a region per block
     if (shape_side(b) >= STREAMED_B && (size_t)nbr * nbc * 7 * (size_t)(8 * b) <= cs.rec_cap) ca.rec = cs.rec;
+    // few blocks on a register-resident coarse level: each block on 2^d - 1 workgroups (same
+    // results); not under stream capture, since a graph would replay the launch's tag
+    if (cs.split_cus > 0 && level_is_lazy(b)) {
+        const int nblk = nbr * nbc;
+        const int d = split_depth(nblk, cs.split_cus, L.G, b);
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (d > 0 && d >= cs.split_min_depth && nblk <= cs.xblocks &&
+            split_slot_words(L.M, L.G, d) <= (size_t)cs.xstride &&
+            hipStreamIsCapturing(L.stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+            if (++cs.xepoch == 0) {   // tags wrapped: clear the words so no old tag can match
+                const hipError_t e = hipMemsetAsync(cs.xslots, 0,
+                                                     sizeof(unsigned long long) * (size_t)cs.xblocks * cs.xstride, L.stream);
+                if (e != hipSuccess) return e;
+                cs.xepoch = 1;
+            }
+            const SplitArgs sa{cs.xslots, (1 << d) - 1, d, cs.xstride, cs.xepoch};
+            return launch_sweep_split(L, u, f, b, pr, pc, nbr, nbc, ca, sa);
+        }
+    }
     if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)
                              : launch_blocks_t<double, 0>(L, u, f, b, pr, pc, nbr, nbc, ca);
     return L.kind ? launch_blocks_t<float, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)

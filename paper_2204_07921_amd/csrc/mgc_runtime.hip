@@ -33,6 +33,9 @@ struct mg_curv_ctx {
 
 namespace {
 
+// the split coarse solve pays for its exchanges from a tree of depth 4 on (15 workgroups per block)
+constexpr int SPLIT_MIN_DEPTH = 4;
+
 thread_local std::string g_init_error;
 
 mg_status fail(mg_curv_ctx* ctx, mg_status st, const char* fmt, ...)
@@ -282,7 +285,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->norm_part = nullptr;
     c->norm_dev = nullptr;
     c->norm_host = nullptr;
-    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0};
+    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr, 0, 0, 0, 0, SPLIT_MIN_DEPTH};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
     const int np = mgc::energy_partials_count(p.height, p.width);
@@ -297,12 +300,40 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     }
     const size_t n_rec = mgc::record_scratch_doubles(p.height, p.width, c->J, p.block_schedule);
     c->coarse.rec_cap = n_rec;
+    // exchange slots of the split coarse solve: one region per block of the largest split
+    // launch, all regions with the stride of the widest tree (fixed, so that a region only
+    // ever holds words tagged by its own generation counter)
+    int cus = 0;
+    size_t xstride = 0, xblocks = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0) {
+        for (int level = 2; level <= c->J; ++level) {
+            const int b = side_at(c, level);
+            if (!mgc::level_is_lazy(b)) continue;
+            const int mj = (p.height + b - 1) / b, nj = (p.width + b - 1) / b;
+            for (int colour = 0; colour < 4; ++colour) {
+                const int nblk = ((mj - (colour >> 1) + 1) / 2) * ((nj - (colour & 1) + 1) / 2);
+                const int d = mgc::split_depth(nblk, cus, p.bisections, b);
+                if (d == 0 || d < SPLIT_MIN_DEPTH) continue;
+                const size_t words = mgc::split_slot_words(p.samples, p.bisections, d);
+                if (words > xstride) xstride = words;
+                if ((size_t)nblk > xblocks) xblocks = (size_t)nblk;
+            }
+        }
+    }
+    bool xok = true;
+    if (xblocks > 0) {   // tag 0 is never used, so cleared words match no launch
+        xok = hipMalloc((void**)&c->coarse.xslots, sizeof(unsigned long long) * xblocks * xstride) == hipSuccess &&
+              hipMemsetAsync(c->coarse.xslots, 0, sizeof(unsigned long long) * xblocks * xstride, c->stream) == hipSuccess;
+        c->coarse.xstride = (int)xstride;
+        c->coarse.xblocks = (int)xblocks;
+        c->coarse.split_cus = cus;
+    }
     if (hipMalloc(&c->pingpong, nb) != hipSuccess || hipMalloc((void**)&c->partials, sizeof(double) * np) != hipSuccess ||
         hipMalloc((void**)&c->coarse.partials, sizeof(double) * n_part) != hipSuccess ||
         hipMalloc((void**)&c->coarse.cpend, sizeof(double) * n_pend) != hipSuccess ||
         hipMalloc((void**)&c->coarse.cpend_alt, sizeof(double) * n_pend) != hipSuccess ||
         (n_rec > 0 && hipMalloc((void**)&c->coarse.rec, sizeof(double) * n_rec) != hipSuccess) ||
-        hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
+        !xok || hipMalloc((void**)&c->energy_dev, sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&c->energy_host, sizeof(double), hipHostMallocDefault) != hipSuccess) {
         mg_curv_destroy(c);
         (void)hipGetLastError();
@@ -447,6 +478,20 @@ mg_status mg_curv_solve_target(mg_curv_ctx* ctx, void* u, const void* f, double 
 
 int32_t mg_curv_levels(const mg_curv_ctx* ctx) { return ctx ? ctx->J : 0; }
 
+mg_status mg_curv_set_split(mg_curv_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return MG_E_INVALID;
+    if (enable != 0 && enable != 1) return fail(ctx, MG_E_INVALID, "enable must be 0 or 1");
+    int cus = 0;
+    if (enable && ctx->coarse.xblocks > 0 &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess)
+        return fail(ctx, MG_E_DEVICE, "device attribute query failed");
+    ctx->coarse.split_cus = (enable && ctx->coarse.xblocks > 0) ? cus : 0;
+    return MG_OK;
+}
+
+int32_t mg_curv_split_active(const mg_curv_ctx* ctx) { return ctx && ctx->coarse.split_cus > 0 ? 1 : 0; }
+
 void mg_curv_destroy(mg_curv_ctx* ctx)
 {
     if (!ctx) return;
@@ -457,6 +502,7 @@ void mg_curv_destroy(mg_curv_ctx* ctx)
     if (ctx->coarse.cpend) (void)hipFree(ctx->coarse.cpend);
     if (ctx->coarse.cpend_alt) (void)hipFree(ctx->coarse.cpend_alt);
     if (ctx->coarse.rec) (void)hipFree(ctx->coarse.rec);
+    if (ctx->coarse.xslots) (void)hipFree(ctx->coarse.xslots);
     if (ctx->energy_dev) (void)hipFree(ctx->energy_dev);
     if (ctx->energy_host) (void)hipHostFree(ctx->energy_host);
     if (ctx->prev) (void)hipFree(ctx->prev);

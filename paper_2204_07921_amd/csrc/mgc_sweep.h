@@ -577,9 +577,10 @@ __host__ __device__ __forceinline__ RingBand ring_band(int H, int W, int r0, int
 
 __host__ __device__ __forceinline__ void band_at(const RingBand& B, int k, int& i, int& j)
 {
-    if (k < B.nt) { i = B.r0 - 1 + k / B.wc; j = B.cl + k % B.wc; return; }
+    // the top and bottom strips are two rows of wc each
+    if (k < B.nt) { const int r = k >= B.wc; i = B.r0 - 1 + r; j = B.cl + k - r * B.wc; return; }
     k -= B.nt;
-    if (k < B.nb) { i = B.r1 - 1 + k / B.wc; j = B.cl + k % B.wc; return; }
+    if (k < B.nb) { const int r = k >= B.wc; i = B.r1 - 1 + r; j = B.cl + k - r * B.wc; return; }
     k -= B.nb;
     const int m = k & (B.per - 1);
     i = B.ra + (B.per == 4 ? k >> 2 : k >> 1);

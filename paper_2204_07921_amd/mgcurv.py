@@ -118,6 +118,10 @@ def _load() -> C.CDLL:
     L.mg_curv_batch_last_error.argtypes = [vp]
     L.mg_curv_levels.restype = C.c_int32
     L.mg_curv_levels.argtypes = [vp]
+    L.mg_curv_set_split.restype = C.c_int
+    L.mg_curv_set_split.argtypes = [vp, C.c_int32]
+    L.mg_curv_split_active.restype = C.c_int32
+    L.mg_curv_split_active.argtypes = [vp]
     L.mg_cnn_num_params.restype = C.c_int32
     L.mg_cnn_num_params.argtypes = []
     L.mg_cnn_init.restype = C.c_int
@@ -302,6 +306,14 @@ def mg_curv_destroy(ctx) -> None:
     lib.mg_curv_destroy(ctx)
 
 
+def mg_curv_set_split(ctx, enable: bool) -> None:
+    _check(lib.mg_curv_set_split(ctx, 1 if enable else 0), ctx)
+
+
+def mg_curv_split_active(ctx) -> bool:
+    return bool(lib.mg_curv_split_active(ctx))
+
+
 # --- convenience object ----------------------------------------------------------
 
 class Solver:
@@ -350,6 +362,13 @@ class Solver:
 
     def level(self, u, f, level):
         return mg_curv_level(self.ctx, self.params, u, f, level)
+
+    def set_split(self, enable: bool) -> None:
+        mg_curv_set_split(self.ctx, enable)
+
+    @property
+    def split_active(self) -> bool:
+        return mg_curv_split_active(self.ctx)
 
 
 # --- the paper's own local step (FBS with tangent-plane estimates) ------------------

@@ -1,0 +1,64 @@
+"""The split coarse-level solve (several workgroups per block, cooperative launch) against the
+one-workgroup solve: bitwise equal states after every V-cycle.
+
+Both compute the arg min of Algorithm 3 (Section 2.2) with the same group sums over the same ring
+records, in the same order of decisions, so the corrections must agree bit for bit.  The oracle
+comparisons of the other GPU tests run with the split solve on (it is the default), so this file
+only ties the two GPU forms together, over shapes whose colours give the split launches different
+tree depths (one, two and four blocks per colour; ragged edges), both block schedules, both
+curvatures and both state types."""
+import numpy as np
+import pytest
+import torch
+
+from synth import noisy_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("shape", [(1024, 1024), (1000, 700), (777, 1030)])
+def test_split_equals_one_workgroup(shape, kind, dtype, schedule):
+    from paper_2204_07921_amd import mgcurv as mg
+    h, w = shape
+    f, _ = noisy_image(h, w, 5, 0.1, dtype=np.float32 if dtype == torch.float32 else np.float64)
+    a = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype, block_schedule=schedule)
+    b = mg.Solver(h, w, alpha=20.0, kind=kind, dtype=dtype, block_schedule=schedule)
+    b.set_split(False)
+    assert a.split_active, "the split solve should be on for this size on a 256-CU device"
+    assert not b.split_active
+    fd = torch.tensor(f, dtype=dtype, device="cuda")
+    ua = fd.clone()
+    ub = fd.clone()
+    for cyc in range(3):
+        _case(f"split vs one workgroup {shape} kind {kind} {dtype} schedule {schedule} V-cycle {cyc}")
+        a.vcycle(ua, fd)
+        b.vcycle(ub, fd)
+        torch.cuda.synchronize()
+        assert torch.isfinite(ua).all()
+        diff = (ua != ub).sum().item()
+        assert diff == 0, f"{diff} pixels differ after V-cycle {cyc}"
+    a.close()
+    b.close()
+
+
+def test_split_switch_round_trip():
+    from paper_2204_07921_amd import mgcurv as mg
+    s = mg.Solver(1024, 1024)
+    assert s.split_active
+    s.set_split(False)
+    assert not s.split_active
+    s.set_split(True)
+    assert s.split_active
+    assert mg.lib.mg_curv_set_split(s.ctx, 2) == -1   # MG_E_INVALID
+    assert s.split_active
+    small = mg.Solver(64, 64)   # no coarse colour with 7 or more workgroups per block fits: nothing to split
+    assert not small.split_active
+    s.close()
+    small.close()
