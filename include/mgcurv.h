@@ -104,7 +104,8 @@ void mg_curv_default_params(mg_curv_params *p, int32_t height, int32_t width);
  * H x W ping-pong image for the pixel level, the energy partial sums, the
  * coarse levels' block sums and two arrays of pending corrections, and, when
  * the levels reach blocks of side >= 1023, the expanded ring records of one
- * colour's blocks (7 doubles per ring pixel; 7.3 MB at 8192 x 8192).
+ * colour's blocks (7 doubles per ring pixel; 7.3 MB at 8192 x 8192), or, for
+ * the split solve below, of each of its workgroups (at most 128 MB).
  * On success *out receives a context the caller releases with
  * mg_curv_destroy.  Errors: MG_E_INVALID / MG_E_SHAPE / MG_E_DTYPE for bad
  * parameters, MG_E_DEVICE without a GPU, MG_E_NOMEM. */
@@ -184,10 +185,11 @@ int32_t mg_curv_levels(const mg_curv_ctx *ctx);
 
 /* Split solve of the coarse levels (the arg min of Algorithm 3, Section 2.2,
  * computed by several workgroups per block).  Where a colour of a coarse
- * level (block side 64..512) holds so few blocks that 2^d - 1 >= 7
- * workgroups per block fit on the device's CUs, each block's samples are
- * spread over its workgroups and its bisection takes d steps per exchange
- * between them.  The corrections are bitwise those of the one-workgroup
+ * level of block side >= 256 holds so few blocks that 2^d - 1 workgroups
+ * per block fit on the device's CUs (d >= 4; for sides >= 1023, whose rings
+ * are streamed from memory, 2 <= d <= 6 within a 128 MB budget of
+ * per-workgroup record copies), each block's samples are spread over its
+ * workgroups and its bisection takes d steps per exchange between them.  The corrections are bitwise those of the one-workgroup
  * solve; only the time differs (a workgroup that waits too long for a value
  * computes it itself, so results never depend on timing).  It is on by
  * default when the context's levels have such colours (mg_curv_init then

@@ -27,7 +27,6 @@ struct CoarseScratch {
     int xstride, xblocks;
     unsigned xepoch;              // tag of the last split launch (0 is never a tag)
     int split_cus;                // workgroups one launch may keep resident (the CU count)
-    int split_min_depth;          // split only when at least this many bisection steps share an exchange
 };
 
 // Exchange slots of one split launch: block k of the launch uses slots[k * stride ..];
@@ -63,8 +62,12 @@ size_t record_scratch_doubles(int H, int W, int J, int schedule);
 // b = 1: colour sweep from uin into uout (every pixel of uout is written).
 hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, const void* f, int colour, int ncolours);
 // Tree depth d of the split solve for a launch of nblocks blocks of side b (0: not split):
-// the largest d <= min(8, G) with nblocks (2^d - 1) <= cus, for register-resident coarse sides >= 256.
+// the largest d <= min(8, G) with nblocks (2^d - 1) <= cus (and, for streamed sides, the
+// workgroups' record copies within a cache-sized budget), for sides >= 256; 0 below depth 4
+// (register-resident rings) or 2 (streamed rings).
 int split_depth(int nblocks, int cus, int G, int b);
+// Record-scratch doubles a split launch of a streamed side needs (one region per workgroup).
+size_t split_record_doubles(int nblocks, int cus, int G, int b);
 // Exchange words one block of a split launch needs: 2 M sample words and ceil(G / d) rounds of 2^d - 1.
 size_t split_slot_words(int M, int G, int d);
 // Coarse colour sweep of nbr x nbc blocks (colour (pr, pc)) by the split solve, P workgroups per block.

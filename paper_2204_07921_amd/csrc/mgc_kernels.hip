@@ -327,8 +327,9 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
         const int nblk = nbr * nbc;
         const int d = split_depth(nblk, cs.split_cus, L.G, b);
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (d > 0 && d >= cs.split_min_depth && nblk <= cs.xblocks &&
-            split_slot_words(L.M, L.G, d) <= (size_t)cs.xstride &&
+        const size_t rec_need = split_record_doubles(nblk, cs.split_cus, L.G, b);
+        if (d > 0 && nblk <= cs.xblocks && split_slot_words(L.M, L.G, d) <= (size_t)cs.xstride &&
+            (shape_side(b) < STREAMED_B || (cs.rec && rec_need <= cs.rec_cap)) &&
             hipStreamIsCapturing(L.stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
             if (++cs.xepoch == 0) {   // tags wrapped: clear the words so no old tag can match
                 const hipError_t e = hipMemsetAsync(cs.xslots, 0,
@@ -337,7 +338,9 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
                 cs.xepoch = 1;
             }
             const SplitArgs sa{cs.xslots, (1 << d) - 1, d, cs.xstride, cs.xepoch};
-            return launch_sweep_split(L, u, f, b, pr, pc, nbr, nbc, ca, sa);
+            CoarseArgs cas = ca;
+            if (shape_side(b) >= STREAMED_B) cas.rec = cs.rec;   // one region per workgroup
+            return launch_sweep_split(L, u, f, b, pr, pc, nbr, nbc, cas, sa);
         }
     }
     if (L.f64) return L.kind ? launch_blocks_t<double, 1>(L, u, f, b, pr, pc, nbr, nbc, ca)

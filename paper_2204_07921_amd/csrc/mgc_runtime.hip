@@ -33,9 +33,6 @@ struct mg_curv_ctx {
 
 namespace {
 
-// the split coarse solve pays for its exchanges from a tree of depth 4 on (15 workgroups per block)
-constexpr int SPLIT_MIN_DEPTH = 4;
-
 thread_local std::string g_init_error;
 
 mg_status fail(mg_curv_ctx* ctx, mg_status st, const char* fmt, ...)
@@ -285,7 +282,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->norm_part = nullptr;
     c->norm_dev = nullptr;
     c->norm_host = nullptr;
-    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr, 0, 0, 0, 0, SPLIT_MIN_DEPTH};
+    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr, 0, 0, 0, 0};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
     const int np = mgc::energy_partials_count(p.height, p.width);
@@ -298,11 +295,10 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
         if ((size_t)nblocks * nchunk > n_part) n_part = (size_t)nblocks * nchunk;
         if ((size_t)nblocks > n_pend) n_pend = (size_t)nblocks;
     }
-    const size_t n_rec = mgc::record_scratch_doubles(p.height, p.width, c->J, p.block_schedule);
-    c->coarse.rec_cap = n_rec;
-    // exchange slots of the split coarse solve: one region per block of the largest split
-    // launch, all regions with the stride of the widest tree (fixed, so that a region only
-    // ever holds words tagged by its own generation counter)
+    size_t n_rec = mgc::record_scratch_doubles(p.height, p.width, c->J, p.block_schedule);
+    // split coarse solve: exchange words for every block of the largest split launch, all
+    // regions with the stride of the widest tree; streamed sides also need one record region
+    // per workgroup of their split launches
     int cus = 0;
     size_t xstride = 0, xblocks = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0) {
@@ -313,13 +309,16 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
             for (int colour = 0; colour < 4; ++colour) {
                 const int nblk = ((mj - (colour >> 1) + 1) / 2) * ((nj - (colour & 1) + 1) / 2);
                 const int d = mgc::split_depth(nblk, cus, p.bisections, b);
-                if (d == 0 || d < SPLIT_MIN_DEPTH) continue;
+                if (d == 0) continue;
                 const size_t words = mgc::split_slot_words(p.samples, p.bisections, d);
+                const size_t recs = mgc::split_record_doubles(nblk, cus, p.bisections, b);
+                if (recs > n_rec) n_rec = recs;
                 if (words > xstride) xstride = words;
                 if ((size_t)nblk > xblocks) xblocks = (size_t)nblk;
             }
         }
     }
+    c->coarse.rec_cap = n_rec;
     bool xok = true;
     if (xblocks > 0) {   // tag 0 is never used, so cleared words match no launch
         xok = hipMalloc((void**)&c->coarse.xslots, sizeof(unsigned long long) * xblocks * xstride) == hipSuccess &&

@@ -44,6 +44,7 @@ namespace mgc {
 namespace {
 
 constexpr int SPLIT_MAX_SAMPLES = 256;   // the largest M the parameters allow
+constexpr double SPLIT_STREAM_BYTES = 128.0 * 1024 * 1024;
 constexpr int SPIN_LIMIT = 1 << 14;      // polls per wait (some milliseconds) before computing a value locally
 
 __device__ __forceinline__ unsigned long long xload(const unsigned long long* p)
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
                                                             int b, int pr, int pc, int nbc, double alpha, int M, int G,
                                                             CoarseArgs ca, SplitArgs sa)
 {
-    static_assert(GROUP % 64 == 0 && RPL > 0, "whole wavefronts, ring in registers");
+    static_assert(GROUP % 64 == 0, "whole wavefronts");
     __shared__ double lds[2 * (GROUP / 64) * BlockSum<GROUP>::NMAX];
     __shared__ unsigned xpay[2 * SPLIT_MAX_SAMPLES];
     __shared__ unsigned char xok[2 * SPLIT_MAX_SAMPLES];
@@ -124,19 +125,36 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
     const int pq = p * ca.nj + q;
     const RingBand band = ring_band(H, W, r0, r1, c0, c1);
     const int ncand = band.n;
-    PolyRing<KIND> rg[RPL];
+    // the ring: RPL records per lane in registers, or (RPL = 0, rings larger than the registers
+    // hold) expanded once into this workgroup's own region of the record scratch and read back
+    // by the lane that wrote them, in the order of the one-workgroup kernel's streamed form
+    PolyRing<KIND> rg[RPL > 0 ? RPL : 1];
+    double* rec = nullptr;
+    if constexpr (RPL > 0) {
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-        const int k = lane + t * GROUP;
-        Ring r;
-        if (k < ncand) {
-            int i, j;
-            band_at(band, k, i, j);
-            make_ring<T, true>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, pq);
-        } else {
-            zero_ring(r);
+        for (int t = 0; t < RPL; ++t) {
+            const int k = lane + t * GROUP;
+            Ring r;
+            if (k < ncand) {
+                int i, j;
+                band_at(band, k, i, j);
+                make_ring<T, true>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, pq);
+            } else {
+                zero_ring(r);
+            }
+            make_poly<KIND>(r, rg[t]);
         }
-        make_poly<KIND>(r, rg[t]);
+    } else {
+        rec = ca.rec + (size_t)blockIdx.x * PolyRing<KIND>::NCOEF * ca.rec_stride;
+        for (int kk = lane; kk < ncand; kk += GROUP) {
+            int i, j;
+            Ring rr;
+            PolyRing<KIND> pr;
+            band_at(band, kk, i, j);
+            make_ring<T, true>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, pq);
+            make_poly<KIND>(rr, pr);
+            store_poly<KIND>(rec, ca.rec_stride, kk, pr);
+        }
     }
     BlockSum<GROUP> gs{lds, 0};
     const double fs = gs(rsum) / s;
@@ -144,18 +162,35 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
         constexpr int N = sizeof(out) / sizeof(double);
 #pragma unroll
         for (int k = 0; k < N; ++k) out[k] = 0.0;
+        if constexpr (RPL > 0) {
 #pragma unroll
-        for (int t = 0; t < RPL; ++t)
-            if (lane + t * GROUP < ncand) {
+            for (int t = 0; t < RPL; ++t)
+                if (lane + t * GROUP < ncand) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
+                    for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
+                }
+        } else {
+            for (int kk = lane; kk < ncand; kk += GROUP) {
+                PolyRing<KIND> pr;
+                load_poly<KIND>(rec, ca.rec_stride, kk, pr);
+#pragma unroll
+                for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(pr, cs[k]);
             }
+        }
     };
     auto Dpart = [&](double c) {
         double acc = 0.0;
+        if constexpr (RPL > 0) {
 #pragma unroll
-        for (int t = 0; t < RPL; ++t)
-            if (lane + t * GROUP < ncand) acc += dabs_poly<KIND>(rg[t], c);
+            for (int t = 0; t < RPL; ++t)
+                if (lane + t * GROUP < ncand) acc += dabs_poly<KIND>(rg[t], c);
+        } else {
+            for (int kk = lane; kk < ncand; kk += GROUP) {
+                PolyRing<KIND> pr;
+                load_poly<KIND>(rec, ca.rec_stride, kk, pr);
+                acc += dabs_poly<KIND>(pr, c);
+            }
+        }
         return acc;
     };
     auto Ksum = [&](double c) {
@@ -303,7 +338,9 @@ hipError_t launch_split_t(const LaunchCtx& L, void* u, const void* f, int b, int
     switch (shape_side(b)) {
     case 256: return launch_split_cfg<T, KIND, 512, 4>(L, u, f, b, pr, pc, nbr, nbc, ca, sa);
     case 512: return launch_split_cfg<T, KIND, 512, 8>(L, u, f, b, pr, pc, nbr, nbc, ca, sa);
-    default: return hipErrorInvalidValue;
+    default:   // streamed sides; the caller has checked that ca.rec holds a region per workgroup
+        if (shape_side(b) < STREAMED_B || !ca.rec) return hipErrorInvalidValue;
+        return launch_split_cfg<T, KIND, 1024, 0>(L, u, f, b, pr, pc, nbr, nbc, ca, sa);
     }
 }
 
@@ -312,10 +349,29 @@ hipError_t launch_split_t(const LaunchCtx& L, void* u, const void* f, int b, int
 int split_depth(int nblocks, int cus, int G, int b)
 {
     const int s = shape_side(b);
-    if (s < 256 || s >= STREAMED_B || nblocks <= 0 || G <= 0) return 0;   // smaller rings: cheaper kept on one CU
+    if (s < 256 || nblocks <= 0 || G <= 0) return 0;   // smaller rings: cheaper kept on one CU
+    const bool streamed = s >= STREAMED_B;
+    // streamed rings: every workgroup keeps its own copy of the block's records (7 doubles per
+    // ring pixel) and streams it at each evaluation; the copies of one launch stay within
+    // SPLIT_STREAM_BYTES and at most 63 workgroups share a block, beyond which the copies'
+    // traffic costs more than the exchanges saved (measured at 2048^2 to 8192^2)
+    const double copy = 7.0 * 8.0 * 8.0 * (double)b;
+    const int dmax = streamed ? 6 : 8;
     int d = 0;
-    while (d < 8 && d < G && (size_t)nblocks * ((2u << d) - 1u) <= (size_t)cus) ++d;
-    return d;
+    while (d < dmax && d < G) {
+        const size_t wg = (size_t)nblocks * ((2u << d) - 1u);
+        if (wg > (size_t)cus || (streamed && (double)wg * copy > SPLIT_STREAM_BYTES)) break;
+        ++d;
+    }
+    // a register-resident ring evaluates in about a microsecond, an exchange costs 1-3: the split
+    // pays from 4 steps per exchange on; a streamed evaluation takes several microseconds
+    return d >= (streamed ? 2 : 4) ? d : 0;
+}
+
+size_t split_record_doubles(int nblocks, int cus, int G, int b)
+{
+    const int d = shape_side(b) >= STREAMED_B ? split_depth(nblocks, cus, G, b) : 0;
+    return d > 0 ? (size_t)nblocks * ((1u << d) - 1u) * 7 * (size_t)(8 * b) : 0;
 }
 
 size_t split_slot_words(int M, int G, int d) { return d > 0 ? 2 * (size_t)M + (size_t)((G + d - 1) / d) * ((1u << d) - 1u) : 0; }

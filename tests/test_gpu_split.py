@@ -5,7 +5,8 @@ Both compute the arg min of Algorithm 3 (Section 2.2) with the same group sums o
 records, in the same order of decisions, so the corrections must agree bit for bit.  The oracle
 comparisons of the other GPU tests run with the split solve on (it is the default), so this file
 only ties the two GPU forms together, over shapes whose colours give the split launches different
-tree depths (one, two and four blocks per colour; ragged edges), both block schedules, both
+tree depths (one, two and four blocks per colour; ragged edges; rings held in registers and rings
+streamed from per-workgroup record copies at sides 1023-2048), both block schedules, both
 curvatures and both state types."""
 import numpy as np
 import pytest
@@ -23,7 +24,7 @@ def _case(msg):
 @pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("kind", [0, 1])
-@pytest.mark.parametrize("shape", [(1024, 1024), (1000, 700), (777, 1030)])
+@pytest.mark.parametrize("shape", [(1024, 1024), (1000, 700), (777, 1030), (2048, 2048), (2100, 1500)])
 def test_split_equals_one_workgroup(shape, kind, dtype, schedule):
     from paper_2204_07921_amd import mgcurv as mg
     h, w = shape
