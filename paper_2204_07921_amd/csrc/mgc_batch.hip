@@ -222,9 +222,11 @@ __global__ __launch_bounds__(256) void batch_apply_kernel(float* __restrict__ u,
     const int nj = side_div(im.W + b - 1, b, lb);
     const size_t n = (size_t)im.H * im.W;
     const double* cp = cpend + pend_off[img];
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t / im.W), j = (int)(t - (size_t)i * im.W);
-        const double c = cp[(size_t)side_div(i, b, lb) * nj + side_div(j, b, lb)];
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    if (t0 >= n) return;
+    PixelWalk pw(t0, stride, im.W);
+    for (size_t t = t0; t < n; t += stride, pw.next()) {
+        const double c = cp[(size_t)side_div(pw.i, b, lb) * nj + side_div(pw.j, b, lb)];
         if (c != 0.0) u[im.off + t] = (float)((double)u[im.off + t] + c);
     }
 }
@@ -244,11 +246,15 @@ __global__ __launch_bounds__(256) void batch_energy_partial_kernel(const float* 
     const float* uu = u + im.off;
     const float* ff = f + im.off;
     double acc = 0.0;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(p / im.W), j = (int)(p - (size_t)i * im.W);
-        const double d = (double)uu[p] - (double)ff[p];
-        const double k = im.kind == 0 ? abs_kappa_at<0>(uu, im.H, im.W, i, j) : abs_kappa_at<1>(uu, im.H, im.W, i, j);
-        acc += k + 0.5 * im.alpha * d * d;
+    const size_t p0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    if (p0 < n) {
+        PixelWalk pw(p0, stride, im.W);
+        for (size_t p = p0; p < n; p += stride, pw.next()) {
+            const double d = (double)uu[p] - (double)ff[p];
+            const double k = im.kind == 0 ? abs_kappa_at<0>(uu, im.H, im.W, pw.i, pw.j)
+                                          : abs_kappa_at<1>(uu, im.H, im.W, pw.i, pw.j);
+            acc += k + 0.5 * im.alpha * d * d;
+        }
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);

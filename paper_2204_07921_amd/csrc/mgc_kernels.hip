@@ -116,8 +116,11 @@ __global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, cons
     const int rb = min(min(ra + rows_per, (p + 1) * b), H);
     double acc = 0.0;
     const int n = (rb > ra ? rb - ra : 0) * w;
+    // element t = threadIdx.x + m blockDim.x of the chunk is pixel (ra + t / w, c0 + t % w);
+    // its row and column advance by the step's quotient and remainder
+    const int si = (int)blockDim.x / w, sj = (int)blockDim.x - si * w;
+    int i = ra + (int)threadIdx.x / w, j = c0 + (int)threadIdx.x % w;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const int i = ra + t / w, j = c0 + t % w;
         const size_t idx = (size_t)i * W + j;
         double v = (double)u[idx];
         if (cprev) {
@@ -129,6 +132,9 @@ __global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, cons
             }
         }
         acc += (double)f[idx] - v;
+        i += si;
+        j += sj;
+        if (j >= c1) { j -= w; ++i; }
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -143,9 +149,11 @@ __global__ __launch_bounds__(256) void apply_level_kernel(T* __restrict__ u, int
                                                           const double* __restrict__ cpend)
 {
     const size_t n = (size_t)H * W;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t / W), j = (int)(t - (size_t)i * W);
-        const double c = cpend[(size_t)side_div(i, b, lb) * nj + side_div(j, b, lb)];
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    if (t0 >= n) return;
+    PixelWalk pw(t0, stride, W);
+    for (size_t t = t0; t < n; t += stride, pw.next()) {
+        const double c = cpend[(size_t)side_div(pw.i, b, lb) * nj + side_div(pw.j, b, lb)];
         if (c != 0.0) u[t] = (T)((double)u[t] + c);
     }
 }
@@ -161,10 +169,13 @@ __global__ __launch_bounds__(256) void energy_partial_kernel(const T* __restrict
     __shared__ double lds[4];
     const size_t n = (size_t)H * W;
     double acc = 0.0;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(p / W), j = (int)(p - (size_t)i * W);
-        const double d = (double)u[p] - (double)f[p];
-        acc += abs_kappa_at<KIND>(u, H, W, i, j) + 0.5 * alpha * d * d;
+    const size_t p0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    if (p0 < n) {
+        PixelWalk pw(p0, stride, W);
+        for (size_t p = p0; p < n; p += stride, pw.next()) {
+            const double d = (double)u[p] - (double)f[p];
+            acc += abs_kappa_at<KIND>(u, H, W, pw.i, pw.j) + 0.5 * alpha * d * d;
+        }
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);

@@ -532,6 +532,25 @@ __device__ __forceinline__ void solve_block2_interior(T* __restrict__ u, const T
     }
 }
 
+// Grid-stride walk over the pixels of an H x W image: pixel p = t, t + stride, ... with its
+// row and column advanced by the stride's quotient and remainder (no division per pixel).
+struct PixelWalk {
+    int i, j, si, sj, W;
+    __device__ __forceinline__ PixelWalk(size_t p0, size_t stride, int W_) : W(W_)
+    {
+        i = (int)(p0 / (size_t)W_);
+        j = (int)(p0 - (size_t)i * W_);
+        si = (int)(stride / (size_t)W_);
+        sj = (int)(stride - (size_t)si * W_);
+    }
+    __device__ __forceinline__ void next()
+    {
+        i += si;
+        j += sj;
+        if (j >= W) { j -= W; ++i; }
+    }
+};
+
 // Block index of pixel coordinate i for block side b (lb = log2(b), or -1 when b
 // is not a power of two).
 __host__ __device__ __forceinline__ int side_div(int i, int b, int lb) { return lb >= 0 ? i >> lb : i / b; }
