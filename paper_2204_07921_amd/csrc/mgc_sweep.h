@@ -638,10 +638,15 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
         const double* part = ca.partials + ((size_t)p * ca.nj + q) * ca.nchunk;
         for (int k = lane; k < ca.nchunk; k += GROUP) rsum += part[k];
     } else {
+        // element k = lane + m GROUP is pixel (r0 + k / w, c0 + k % w), advanced incrementally
+        const int si = GROUP / w, sj = GROUP - si * w;
+        int i = r0 + lane / w, j = c0 + lane % w;
         for (int k = lane; k < h * w; k += GROUP) {
-            const int i = r0 + k / w, j = c0 + k % w;
             const size_t idx = (size_t)i * W + j;
             rsum += (double)f[idx] - (double)u[idx];
+            i += si;
+            j += sj;
+            if (j >= c1) { j -= w; ++i; }
         }
     }
     // the group total of rsum (and with it f*) is taken after the ring records are built, so the
@@ -759,10 +764,14 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
     if (LAZY) {
         if (lane == 0) ca.cpend[(size_t)p * ca.nj + q] = cval;
     } else if (cval != 0.0) {
+        const int si = GROUP / w, sj = GROUP - si * w;
+        int i = r0 + lane / w, j = c0 + lane % w;
         for (int k = lane; k < h * w; k += GROUP) {
-            const int i = r0 + k / w, j = c0 + k % w;
             const size_t idx = (size_t)i * W + j;
             u[idx] = (T)((double)u[idx] + cval);
+            i += si;
+            j += sj;
+            if (j >= c1) { j -= w; ++i; }
         }
     }
 }
