@@ -277,32 +277,20 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
         const int ihi = istar < M ? istar + 1 : M;
         double lo = fs + rho * frac(ilo);
         double hi = fs + rho * frac(ihi);
-        // midpoint of tree node `node` (1 = the round's root) of the bracket [a, z]
-        auto node_mid = [](int node, double a, double z) {
-            for (int k = 30 - __clz(node); k >= 0; --k) {   // the path below the root
-                const double mid = 0.5 * (a + z);
-                if ((node >> k) & 1) a = mid; else z = mid;
-            }
-            return 0.5 * (a + z);
-        };
         auto sign_at = [&](double mid) { return gs(Dpart(mid)) + as * (mid - fs) > 0.0; };
         unsigned long long* rs = slots + 2 * M;
         for (int g0 = 0; g0 < G; g0 += d, rs += P) {
             const int dd = min(d, G - g0);
             const int nn = (1 << dd) - 1;
             if (w < nn) {
-                const bool sg = sign_at(node_mid(w + 1, lo, hi));
+                const bool sg = sign_at(tree_node_mid(w + 1, lo, hi));
                 if (lane == 0) xstore(rs + w, tagged(tag, sg ? 1u : 0u));
             }
             if (lane < 64) gather_words(rs, nn, tag, xpay, xok);
             __syncthreads();
-            int node = 1;
-            for (int k = 0; k < dd; ++k) {
-                const double mid = 0.5 * (lo + hi);   // node's midpoint: [lo, hi] is its interval here
-                const bool pos = xok[node - 1] ? xpay[node - 1] != 0u : sign_at(mid);
-                if (pos) { hi = mid; node = 2 * node; }
-                else { lo = mid; node = 2 * node + 1; }
-            }
+            tree_walk(dd, lo, hi, [&](int node, double mid) {
+                return xok[node - 1] ? xpay[node - 1] != 0u : sign_at(mid);
+            });
             __syncthreads();   // every wave has read this round's words before the next round's
         }
         if (w != 0) return;

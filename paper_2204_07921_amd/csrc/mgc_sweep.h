@@ -551,6 +551,37 @@ struct PixelWalk {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Bisection tree of the split coarse solve.  d successive bisection steps from
+// the bracket [lo, hi] visit d of the 2^d - 1 midpoints of a binary tree: node 1
+// is the bracket's midpoint, and node n's children 2n and 2n + 1 are the
+// midpoints of the lower half of n's interval (taken when V' > 0 at n, as a step
+// then sets hi = mid) and of its upper half.  tree_node_mid forms node n's
+// midpoint from [lo, hi] along the path to n exactly as the steps would;
+// tree_walk takes d steps along given signs, moving [lo, hi] as d sequential
+// steps do.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ double tree_node_mid(int node, double lo, double hi)
+{
+    for (int k = 30 - __builtin_clz((unsigned)node); k >= 0; --k) {   // the path below the root
+        const double mid = 0.5 * (lo + hi);
+        if ((node >> k) & 1) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// pos(node, mid): whether V' > 0 at that node, whose midpoint is mid.
+template <class Pos>
+__host__ __device__ __forceinline__ void tree_walk(int d, double& lo, double& hi, Pos&& pos)
+{
+    int node = 1;
+    for (int k = 0; k < d; ++k) {
+        const double mid = 0.5 * (lo + hi);   // node's midpoint: [lo, hi] is its interval here
+        if (pos(node, mid)) { hi = mid; node = 2 * node; }
+        else { lo = mid; node = 2 * node + 1; }
+    }
+}
+
 // Block index of pixel coordinate i for block side b (lb = log2(b), or -1 when b
 // is not a power of two).
 __host__ __device__ __forceinline__ int side_div(int i, int b, int lb) { return lb >= 0 ? i >> lb : i / b; }

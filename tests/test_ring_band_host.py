@@ -63,3 +63,18 @@ def test_oracle_is_clean_under_sanitizers(tmp_path):
     sys.stdout.write(r.stdout + r.stderr[-2000:])
     assert r.returncode == 0, r.stderr[-4000:]
     assert "sanitized runs" in r.stdout
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
+def test_split_tree_and_depth_host_check(tmp_path):
+    """The split coarse solve's bisection tree against sequential bisection (bitwise, d = 1..8,
+    G = 0..64, monotone and arbitrary signs) and its depth choice against its constraints."""
+    exe = str(tmp_path / "split_tree_check")
+    subprocess.check_call([_hipcc(), "-x", "hip", "--offload-arch=gfx950", "-O1", "-std=c++17",
+                           "-Wno-unused-command-line-argument",
+                           os.path.join(HERE, "host", "split_tree_check.cpp"), "-o", exe],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    sys.stdout.write(r.stdout)
+    assert r.returncode == 0, r.stdout
+    assert "bad 0" in r.stdout
