@@ -1,7 +1,8 @@
 // Coarse levels with one block solved by several workgroups (gfx950).
 //
 // On the coarse levels of an image the size of the 1024 x 1024 workload a
-// colour holds few blocks (one at b = 512, four at b = 256), so the one-
+// colour holds few blocks (one at b = 512, four at b = 256; larger images
+// reach such colours at larger sides), so the one-
 // workgroup-per-block sweep keeps a handful of the 256 CUs busy while each
 // block's 51 ring evaluations (K(0) and K(f*), M samples, G bisection steps,
 // the final K) run one after another on its CU.  Here one block is solved by
@@ -18,6 +19,11 @@
 //     it.  Workgroup w takes the sign of V' at node w + 1; after the exchange
 //     every workgroup walks the tree along the signs, which moves the bracket
 //     exactly as d sequential steps would.
+//
+// Rings too large for the registers (sides from 1023 on) are streamed: each
+// workgroup expands the whole ring once into its own region of the record
+// scratch and reads it back at every evaluation, so no record written by one
+// CU has to be seen by another.
 //
 // Every evaluation is the same group sum over the same records as in the
 // one-workgroup kernel (sweep_blocks_kernel with LAZY), and the decisions are
