@@ -63,3 +63,31 @@ def test_split_switch_round_trip():
     assert not small.split_active
     s.close()
     small.close()
+
+
+@pytest.mark.parametrize("samples,bisections", [(10, 7), (2, 5), (256, 64), (6, 4)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_split_equals_one_workgroup_other_search_constants(samples, bisections, dtype):
+    """M not a power of two (the sample offsets are quotients), M below the workgroups per block,
+    G below the tree depth of 6 and 8 (partial rounds; the split needs G >= 4), and the largest M
+    and G the parameters allow (512 sample words)."""
+    from paper_2204_07921_amd import mgcurv as mg
+    h, w = 1024, 1024
+    f, _ = noisy_image(h, w, 9, 0.1, dtype=np.float32 if dtype == torch.float32 else np.float64)
+    kw = dict(alpha=20.0, kind=0, dtype=dtype, samples=samples, bisections=bisections)
+    a = mg.Solver(h, w, **kw)
+    b = mg.Solver(h, w, **kw)
+    b.set_split(False)
+    assert a.split_active
+    fd = torch.tensor(f, dtype=dtype, device="cuda")
+    ua = fd.clone()
+    ub = fd.clone()
+    for cyc in range(2):
+        _case(f"split vs one workgroup M {samples} G {bisections} {dtype} V-cycle {cyc}")
+        a.vcycle(ua, fd)
+        b.vcycle(ub, fd)
+        torch.cuda.synchronize()
+        assert torch.isfinite(ua).all()
+        assert torch.equal(ua, ub)
+    a.close()
+    b.close()
