@@ -203,6 +203,16 @@ mg_status mg_curv_set_split(mg_curv_ctx *ctx, int32_t enable);
 /* 1 if the context's coarse levels use the split solve, else 0 (also for NULL). */
 int32_t mg_curv_split_active(const mg_curv_ctx *ctx);
 
+/* Bound on the polls of each exchange wait of the split solve (default 16384,
+ * some milliseconds).  A workgroup that has not seen a value within the bound
+ * evaluates it itself, with the same records and sums, so the corrections do
+ * not depend on this setting; 0 makes every workgroup evaluate every value
+ * (each block then costs what it costs on one workgroup).  Meant for tests of
+ * that fallback and for shared devices where workgroups of one launch may not
+ * run at the same time.  Returns MG_OK, or MG_E_INVALID for a null context or
+ * polls < 0. */
+mg_status mg_curv_set_split_polls(mg_curv_ctx *ctx, int32_t polls);
+
 /* Release the context (NULL is allowed).  Waits for its stream first. */
 void mg_curv_destroy(mg_curv_ctx *ctx);
 

@@ -27,6 +27,7 @@ struct CoarseScratch {
     int xstride, xblocks;
     unsigned xepoch;              // tag of the last split launch (0 is never a tag)
     int split_cus;                // workgroups one launch may keep resident (the CU count)
+    int split_polls;              // bound on the polls of one exchange wait
 };
 
 // Exchange slots of one split launch: block k of the launch uses slots[k * stride ..];
@@ -36,6 +37,7 @@ struct SplitArgs {
     int P, d;
     int stride;
     unsigned tag;
+    int polls;    // bound on the polls of one wait; a value not seen by then is computed locally
 };
 
 // Block side at level j (1-based): 2^(j-1) (schedule 0, nested blocks) or 2^j - 1
@@ -68,6 +70,8 @@ hipError_t launch_sweep_pixels(const LaunchCtx& L, const void* uin, void* uout, 
 int split_depth(int nblocks, int cus, int G, int b);
 // Record-scratch doubles a split launch of a streamed side needs (one region per workgroup).
 size_t split_record_doubles(int nblocks, int cus, int G, int b);
+// Polls of one exchange wait by default (some milliseconds).
+constexpr int SPLIT_POLLS = 1 << 14;
 // Exchange words one block of a split launch needs: 2 M sample words and ceil(G / d) rounds of 2^d - 1.
 size_t split_slot_words(int M, int G, int d);
 // Coarse colour sweep of nbr x nbc blocks (colour (pr, pc)) by the split solve, P workgroups per block.

@@ -348,7 +348,7 @@ hipError_t launch_sweep_blocks(const LaunchCtx& L, void* u, const void* f, int b
                 if (e != hipSuccess) return e;
                 cs.xepoch = 1;
             }
-            const SplitArgs sa{cs.xslots, (1 << d) - 1, d, cs.xstride, cs.xepoch};
+            const SplitArgs sa{cs.xslots, (1 << d) - 1, d, cs.xstride, cs.xepoch, cs.split_polls};
             CoarseArgs cas = ca;
             if (shape_side(b) >= STREAMED_B) cas.rec = cs.rec;   // one region per workgroup
             return launch_sweep_split(L, u, f, b, pr, pc, nbr, nbc, cas, sa);

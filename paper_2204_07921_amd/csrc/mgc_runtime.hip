@@ -282,7 +282,7 @@ mg_status mg_curv_init(const mg_curv_params* params, void* hip_stream, mg_curv_c
     c->norm_part = nullptr;
     c->norm_dev = nullptr;
     c->norm_host = nullptr;
-    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr, 0, 0, 0, 0};
+    c->coarse = mgc::CoarseScratch{nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr, 0, 0, 0, 0, mgc::SPLIT_POLLS};
     (void)hipGetDevice(&c->device);
     const size_t nb = state_bytes(c);
     const int np = mgc::energy_partials_count(p.height, p.width);
@@ -490,6 +490,14 @@ mg_status mg_curv_set_split(mg_curv_ctx* ctx, int32_t enable)
 }
 
 int32_t mg_curv_split_active(const mg_curv_ctx* ctx) { return ctx && ctx->coarse.split_cus > 0 ? 1 : 0; }
+
+mg_status mg_curv_set_split_polls(mg_curv_ctx* ctx, int32_t polls)
+{
+    if (!ctx) return MG_E_INVALID;
+    if (polls < 0) return fail(ctx, MG_E_INVALID, "polls must be >= 0");
+    ctx->coarse.split_polls = polls;
+    return MG_OK;
+}
 
 void mg_curv_destroy(mg_curv_ctx* ctx)
 {

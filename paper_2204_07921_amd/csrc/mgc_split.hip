@@ -51,7 +51,6 @@ namespace {
 
 constexpr int SPLIT_MAX_SAMPLES = 256;   // the largest M the parameters allow
 constexpr double SPLIT_STREAM_BYTES = 128.0 * 1024 * 1024;
-constexpr int SPIN_LIMIT = 1 << 14;      // polls per wait (some milliseconds) before computing a value locally
 
 __device__ __forceinline__ unsigned long long xload(const unsigned long long* p)
 {
@@ -69,9 +68,9 @@ __device__ __forceinline__ unsigned long long tagged(unsigned tag, unsigned payl
 }
 
 // Wave 0 (lanes 0..63): wait until words [0, n) of `base` carry `tag` (n <= 512; lane t
-// owns words t, t + 64, ...), polling all of a lane's words at once.  payload[k] receives
-// word k's low half and ok[k] whether it arrived within the bounded wait.
-__device__ __forceinline__ void gather_words(const unsigned long long* base, int n, unsigned tag,
+// owns words t, t + 64, ...), polling all of a lane's words at once, at most `polls` times.
+// payload[k] receives word k's low half and ok[k] whether it arrived within the wait.
+__device__ __forceinline__ void gather_words(const unsigned long long* base, int n, unsigned tag, int polls,
                                              unsigned* payload, unsigned char* ok)
 {
     constexpr int PER = 8;
@@ -80,7 +79,7 @@ __device__ __forceinline__ void gather_words(const unsigned long long* base, int
 #pragma unroll
     for (int k = 0; k < PER; ++k)
         if (lane + 64 * k < n) need |= 1u << k;
-    for (int it = 0; it < SPIN_LIMIT && done != need; ++it) {
+    for (int it = 0; it < polls && done != need; ++it) {
         unsigned long long v[PER];
         const unsigned open = need & ~done;
 #pragma unroll
@@ -244,7 +243,7 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
             }
         }
         if (lane < 64) {
-            gather_words(slots, 2 * M, tag, xpay, xok);
+            gather_words(slots, 2 * M, tag, sa.polls, xpay, xok);
             bool all = true;
             for (int t = lane; t < M; t += 64) {
                 ksamp[t] = __longlong_as_double((long long)(((unsigned long long)xpay[2 * t] << 32) | xpay[2 * t + 1]));
@@ -292,7 +291,7 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
                 const bool sg = sign_at(tree_node_mid(w + 1, lo, hi));
                 if (lane == 0) xstore(rs + w, tagged(tag, sg ? 1u : 0u));
             }
-            if (lane < 64) gather_words(rs, nn, tag, xpay, xok);
+            if (lane < 64) gather_words(rs, nn, tag, sa.polls, xpay, xok);
             __syncthreads();
             tree_walk(dd, lo, hi, [&](int node, double mid) {
                 return xok[node - 1] ? xpay[node - 1] != 0u : sign_at(mid);

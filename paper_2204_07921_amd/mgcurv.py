@@ -122,6 +122,8 @@ def _load() -> C.CDLL:
     L.mg_curv_set_split.argtypes = [vp, C.c_int32]
     L.mg_curv_split_active.restype = C.c_int32
     L.mg_curv_split_active.argtypes = [vp]
+    L.mg_curv_set_split_polls.restype = C.c_int
+    L.mg_curv_set_split_polls.argtypes = [vp, C.c_int32]
     L.mg_cnn_num_params.restype = C.c_int32
     L.mg_cnn_num_params.argtypes = []
     L.mg_cnn_init.restype = C.c_int
@@ -314,6 +316,10 @@ def mg_curv_split_active(ctx) -> bool:
     return bool(lib.mg_curv_split_active(ctx))
 
 
+def mg_curv_set_split_polls(ctx, polls: int) -> None:
+    _check(lib.mg_curv_set_split_polls(ctx, int(polls)), ctx)
+
+
 # --- convenience object ----------------------------------------------------------
 
 class Solver:
@@ -369,6 +375,9 @@ class Solver:
     @property
     def split_active(self) -> bool:
         return mg_curv_split_active(self.ctx)
+
+    def set_split_polls(self, polls: int) -> None:
+        mg_curv_set_split_polls(self.ctx, polls)
 
 
 # --- the paper's own local step (FBS with tangent-plane estimates) ------------------

@@ -91,3 +91,32 @@ def test_split_equals_one_workgroup_other_search_constants(samples, bisections, 
         assert torch.equal(ua, ub)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("polls", [0, 1, 4])
+@pytest.mark.parametrize("shape", [(1024, 1024), (2048, 2048)])
+def test_split_local_fallback_is_bitwise_equal(shape, polls):
+    """Exchange waits cut short from the host: with 0 polls every workgroup evaluates every sample
+    and tree node itself; with 1 or 4 polls some values arrive in time and the rest are evaluated
+    locally, a mix that depends on timing.  The corrections must not depend on it (register and
+    streamed rings)."""
+    from paper_2204_07921_amd import mgcurv as mg
+    h, w = shape
+    f, _ = noisy_image(h, w, 13, 0.1, dtype=np.float32)
+    a = mg.Solver(h, w, alpha=20.0, kind=0)
+    b = mg.Solver(h, w, alpha=20.0, kind=0)
+    a.set_split_polls(polls)
+    b.set_split(False)
+    assert a.split_active
+    fd = torch.tensor(f, device="cuda")
+    ua = fd.clone()
+    ub = fd.clone()
+    for cyc in range(2):
+        _case(f"split with {polls} polls per wait {shape} V-cycle {cyc}")
+        a.vcycle(ua, fd)
+        b.vcycle(ub, fd)
+        torch.cuda.synchronize()
+        assert torch.equal(ua, ub)
+    assert mg.lib.mg_curv_set_split_polls(a.ctx, -1) == -1   # MG_E_INVALID
+    a.close()
+    b.close()
