@@ -120,3 +120,29 @@ def test_split_local_fallback_is_bitwise_equal(shape, polls):
     assert mg.lib.mg_curv_set_split_polls(a.ctx, -1) == -1   # MG_E_INVALID
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("shape", [(260, 4100), (4100, 260)])
+def test_split_equals_one_workgroup_clipped_blocks(shape, kind):
+    """Long thin images: colours of 3-9 blocks at sides 256-1024 and single blocks clipped to a
+    few pixels across (260 x 4096 and 260 x 4 at side 4096), register and streamed rings."""
+    from paper_2204_07921_amd import mgcurv as mg
+    h, w = shape
+    f, _ = noisy_image(h, w, 17, 0.1, dtype=np.float32)
+    a = mg.Solver(h, w, alpha=20.0, kind=kind)
+    b = mg.Solver(h, w, alpha=20.0, kind=kind)
+    b.set_split(False)
+    assert a.split_active
+    fd = torch.tensor(f, device="cuda")
+    ua = fd.clone()
+    ub = fd.clone()
+    for cyc in range(2):
+        _case(f"split vs one workgroup {shape} kind {kind} V-cycle {cyc}")
+        a.vcycle(ua, fd)
+        b.vcycle(ub, fd)
+        torch.cuda.synchronize()
+        assert torch.isfinite(ua).all()
+        assert torch.equal(ua, ub)
+    a.close()
+    b.close()
