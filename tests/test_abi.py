@@ -94,6 +94,20 @@ def test_null_arguments(lib):
     lib.mg_curv_destroy(None)
 
 
+def test_split_controls_reject_a_null_context(lib):
+    """The split coarse solve's switch, status query and wait bound check their context first."""
+    lib.mg_curv_set_split.restype = C.c_int
+    lib.mg_curv_set_split.argtypes = [C.c_void_p, C.c_int32]
+    lib.mg_curv_set_split_polls.restype = C.c_int
+    lib.mg_curv_set_split_polls.argtypes = [C.c_void_p, C.c_int32]
+    lib.mg_curv_split_active.restype = C.c_int32
+    lib.mg_curv_split_active.argtypes = [C.c_void_p]
+    assert lib.mg_curv_set_split(None, 1) == -1
+    assert lib.mg_curv_set_split(None, 0) == -1
+    assert lib.mg_curv_set_split_polls(None, 16) == -1
+    assert lib.mg_curv_split_active(None) == 0
+
+
 def test_no_device_reports_device_error(lib):
     import torch
     if torch.cuda.is_available():
