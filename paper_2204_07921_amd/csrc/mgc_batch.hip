@@ -132,12 +132,15 @@ __device__ __forceinline__ void batch_block_item(float* __restrict__ u, const fl
         const int r1 = min(r0 + a.b, im.H), c1 = min(c0 + a.b, im.W);
         CoarseArgs ca{LAZY ? a.partials + a.part_off[img] : nullptr, a.nchunk, LAZY ? a.cpend + a.pend_off[img] : nullptr,
                       nj, nullptr, 8 * a.b};
+        // both curvatures share this kernel's registers: the widest shapes build their rings in
+        // smaller chunks
+        constexpr int CH = GROUP >= 1024 ? 1 : (RPL >= 8 ? 2 : ring_chunk<float, GROUP>());
         if (im.kind == 0)
-            solve_block<float, 0, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
-                                                    im.alpha, M, G, gs, ca);
+            solve_block<float, 0, GROUP, RPL, LAZY, CH>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
+                                                        im.alpha, M, G, gs, ca);
         else
-            solve_block<float, 1, GROUP, RPL, LAZY>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
-                                                    im.alpha, M, G, gs, ca);
+            solve_block<float, 1, GROUP, RPL, LAZY, CH>(u + im.off, f + im.off, im.H, im.W, p, q, r0, r1, c0, c1, lane,
+                                                        im.alpha, M, G, gs, ca);
     }
 }
 

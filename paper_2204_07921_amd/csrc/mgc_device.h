@@ -43,59 +43,117 @@ __device__ __forceinline__ void stencil5(const double t[3][3], double d[5])
     d[4] = 0.25 * ((t[2][2] - t[0][2]) - (t[2][0] - t[0][0]));
 }
 
-// Value of tap (i, j) (already clamped) as the sweep sees it.  With pending
-// corrections (coarse levels apply a level's corrections lazily) the value is
-// u + c_pending of the tap's block (index k), rounded to the state type exactly
-// as an eager update would have stored it.
-template <typename T, bool LAZY>
-__device__ __forceinline__ double tap_value(const T* __restrict__ u, int W, int i, int j,
-                                            const double* __restrict__ cpend, int k)
-{
-    const double v = (double)u[(size_t)i * W + j];
-    if (!LAZY) return v;
-    return (double)(T)(v + cpend[k]);
-}
-
 // Index in the m_j x n_j pending corrections of the block holding tap (ci, cj)
 // (clamped into the image) of a ring pixel of block B = rows [r0, r1) x cols
 // [c0, c1), pq = p nj + q.  A ring pixel lies within one pixel of B and a tap
 // within one pixel of it, so for b >= 2 a tap above (below, left of, right of) B
 // lies in the neighbouring block on that side: comparisons give the index for
 // any block side, powers of two or not.
+// Side of v against [lo, hi) (lo < hi): -1 below, +1 at or above hi, 0 inside; and
+// 1 inside, 0 outside.  Taken from sign bits, so a lane computes them without
+// compare masks (which, for the nine taps of several records, outgrow the scalar
+// registers).
+__host__ __device__ __forceinline__ int side_of(int v, int lo, int hi)
+{
+    return ((v - lo) >> 31) - ((hi - 1 - v) >> 31);
+}
+__host__ __device__ __forceinline__ int inside_of(int v, int lo, int hi)
+{
+    return 1 + ((v - lo) >> 31) + ((hi - 1 - v) >> 31);
+}
+
 __host__ __device__ __forceinline__ int tap_block(int pq, int nj, int ci, int cj, int r0, int r1, int c0, int c1)
 {
-    return pq + (ci < r0 ? -nj : (ci >= r1 ? nj : 0)) + (cj < c0 ? -1 : (cj >= c1 ? 1 : 0));
+    return pq + side_of(ci, r0, r1) * nj + side_of(cj, c0, c1);
+}
+
+// The nine clamped taps of pixel (i, j) as loaded from memory (and, LAZY, the
+// pending correction of the block each lies in): the first half of a ring
+// record.  Kept apart from the arithmetic so that a lane can put the loads of
+// several records in flight before it uses any of them.  mask: bit 3 (dy + 1) +
+// (dx + 1) is set when tap (dy, dx) lies inside B, bit 9 when (i, j) lies inside
+// the image.
+template <typename T, bool LAZY>
+struct RingTaps {
+    T v[3][3];
+    double cp[LAZY ? 3 : 1][LAZY ? 3 : 1];
+    int mask;
+};
+
+// Loads the taps of pixel (i, j) for block rows [r0, r1) x cols [c0, c1).  Every
+// address is clamped into the image, so any (i, j) may be passed.
+template <typename T, bool LAZY>
+__device__ __forceinline__ void load_taps(const T* __restrict__ u, int H, int W, int i, int j, int r0, int r1,
+                                          int c0, int c1, RingTaps<T, LAZY>& tp,
+                                          const double* __restrict__ cpend, int nj, int pq)
+{
+    int mask = (inside_of(i, 0, H) & inside_of(j, 0, W)) << 9;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int ci = clampi(i + dy, 0, H - 1);
+        const int rin = inside_of(ci, r0, r1);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int cj = clampi(j + dx, 0, W - 1);
+            tp.v[dy + 1][dx + 1] = u[(size_t)ci * W + cj];
+            if constexpr (LAZY) tp.cp[dy + 1][dx + 1] = cpend[tap_block(pq, nj, ci, cj, r0, r1, c0, c1)];
+            mask |= (rin & inside_of(cj, c0, c1)) << (3 * (dy + 1) + (dx + 1));
+        }
+    }
+    tp.mask = mask;
+}
+
+// The ring record from loaded taps.  With pending corrections (coarse levels
+// apply a level's corrections lazily) a tap's value is u + c_pending of its
+// block, rounded to the state type exactly as an eager update would have stored
+// it.  Pixels outside the image, pixels whose nine clamped taps lie all inside
+// or all outside B (their curvature does not depend on c), and any pixel with
+// use = false get the zero record, which contributes exactly 0 to every sum
+// below.  The slopes are the stencil of the 0/1 mask of taps inside B, formed
+// in integers (the same small exact values as the FP64 stencil of the mask);
+// the zero record is selected at the end rather than branched to, so the build
+// takes no divergent paths.
+template <typename T, bool LAZY>
+__device__ __forceinline__ void ring_from_taps(const RingTaps<T, LAZY>& tp, Ring& r, bool use = true)
+{
+    double t[3][3];
+    int m[3][3];
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const double v = (double)tp.v[y][x];
+            if constexpr (LAZY) t[y][x] = (double)(T)(v + tp.cp[y][x]);
+            else t[y][x] = v;
+            m[y][x] = (tp.mask >> (3 * y + x)) & 1;
+        }
+    const int n = __builtin_popcount(tp.mask & 511);
+    const bool keep = use && (tp.mask >> 9) != 0 && n != 0 && n != 9;
+    double a[5], bs[5];
+    stencil5(t, a);
+    bs[0] = 0.5 * (double)(m[1][2] - m[1][0]);
+    bs[1] = 0.5 * (double)(m[2][1] - m[0][1]);
+    bs[2] = (double)(m[1][2] + m[1][0] - 2 * m[1][1]);
+    bs[3] = (double)(m[2][1] + m[0][1] - 2 * m[1][1]);
+    bs[4] = 0.25 * (double)((m[2][2] - m[0][2]) - (m[2][0] - m[0][0]));
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        r.a[k] = keep ? a[k] : 0.0;
+        r.b[k] = keep ? bs[k] : 0.0;
+    }
 }
 
 // Build the ring record of pixel (i, j) for block rows [r0, r1) x cols [c0, c1).
-// Pixels outside the image, and pixels whose nine clamped taps lie all inside or
-// all outside B (their curvature does not depend on c), get the zero record,
-// which contributes exactly 0 to every sum below.  LAZY: pq = p nj + q (see tap_block).
+// LAZY: pq = p nj + q (see tap_block).
 template <typename T, bool LAZY = false>
 __device__ __forceinline__ void make_ring(const T* __restrict__ u, int H, int W, int i, int j,
                                           int r0, int r1, int c0, int c1, Ring& r,
                                           const double* __restrict__ cpend = nullptr, int nj = 0, int pq = 0)
 {
     if (i < 0 || i >= H || j < 0 || j >= W) { zero_ring(r); return; }
-    double t[3][3], m[3][3];
-    int n = 0;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int ci = clampi(i + dy, 0, H - 1);
-        const bool rin = ci >= r0 && ci < r1;
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int cj = clampi(j + dx, 0, W - 1);
-            const bool in = rin && cj >= c0 && cj < c1;
-            const int k = LAZY ? tap_block(pq, nj, ci, cj, r0, r1, c0, c1) : 0;
-            t[dy + 1][dx + 1] = tap_value<T, LAZY>(u, W, ci, cj, cpend, k);
-            m[dy + 1][dx + 1] = in ? 1.0 : 0.0;
-            n += in ? 1 : 0;
-        }
-    }
-    if (n == 0 || n == 9) { zero_ring(r); return; }
-    stencil5(t, r.a);
-    stencil5(m, r.b);
+    RingTaps<T, LAZY> tp;
+    load_taps<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, tp, cpend, nj, pq);
+    ring_from_taps<T, LAZY>(tp, r);
 }
 
 // |kappa| of a ring record at shift c.

@@ -136,30 +136,10 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
     PolyRing<KIND> rg[RPL > 0 ? RPL : 1];
     double* rec = nullptr;
     if constexpr (RPL > 0) {
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int k = lane + t * GROUP;
-            Ring r;
-            if (k < ncand) {
-                int i, j;
-                band_at(band, k, i, j);
-                make_ring<T, true>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, pq);
-            } else {
-                zero_ring(r);
-            }
-            make_poly<KIND>(r, rg[t]);
-        }
+        ring_to_regs<T, KIND, GROUP, RPL, true>(u, H, W, band, lane, ca.cpend, ca.nj, pq, rg);
     } else {
         rec = ca.rec + (size_t)blockIdx.x * PolyRing<KIND>::NCOEF * ca.rec_stride;
-        for (int kk = lane; kk < ncand; kk += GROUP) {
-            int i, j;
-            Ring rr;
-            PolyRing<KIND> pr;
-            band_at(band, kk, i, j);
-            make_ring<T, true>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, pq);
-            make_poly<KIND>(rr, pr);
-            store_poly<KIND>(rec, ca.rec_stride, kk, pr);
-        }
+        ring_to_region<T, KIND, GROUP, true>(u, H, W, band, lane, ca.cpend, ca.nj, pq, rec, ca.rec_stride);
     }
     BlockSum<GROUP> gs{lds, 0};
     const double fs = gs(rsum) / s;

@@ -637,6 +637,91 @@ __host__ __device__ __forceinline__ void band_at(const RingBand& B, int k, int& 
     j = (B.left && m < 2) ? B.c0 - 1 + m : B.c1 - 1 + (m & 1);
 }
 
+// Ring records built in chunks: a lane loads the taps of a chunk of its records
+// (band positions k, k + GROUP, ...) before it forms any of them, so their
+// memory round trips overlap instead of following one another.  A position at
+// or past the band's end loads the taps of position 0 (clamped addresses, in
+// bounds for any band) and gets the zero record.  The records are make_ring's,
+// bit for bit.  A chunk is four records, fewer where registers are short: FP64
+// taps take twice the registers, and 1,024-lane workgroups have 128 per lane.
+template <typename T, int GROUP>
+constexpr int ring_chunk()
+{
+    return (GROUP >= 1024 ? 2 : 4) / (sizeof(T) == 8 ? 2 : 1);
+}
+
+// Slot t of a lane's registers holds band position lane + t GROUP.  Each chunk
+// sits under a branch on its first position: a chunk wholly past the band's end
+// takes the zero records without loading, and the compiler cannot hoist a later
+// chunk's loads above the branch, so no more than one chunk of taps is live.
+template <typename T, int KIND, int GROUP, int RPL, bool LAZY, int CHUNK = ring_chunk<T, GROUP>()>
+__device__ __forceinline__ void ring_to_regs(const T* __restrict__ u, int H, int W, const RingBand& band, int lane,
+                                             const double* __restrict__ cpend, int nj, int pq,
+                                             PolyRing<KIND> (&rg)[RPL])
+{
+    constexpr int CH = RPL < CHUNK ? RPL : CHUNK;
+#pragma unroll
+    for (int t0 = 0; t0 < RPL; t0 += CH) {
+        if (lane + t0 * GROUP < band.n) {
+            RingTaps<T, LAZY> tp[CH];
+#pragma unroll
+            for (int s = 0; s < CH; ++s) {
+                if (t0 + s >= RPL) break;
+                const int k = lane + (t0 + s) * GROUP;
+                int i, j;
+                band_at(band, k < band.n ? k : 0, i, j);
+                load_taps<T, LAZY>(u, H, W, i, j, band.r0, band.r1, band.c0, band.c1, tp[s], cpend, nj, pq);
+            }
+#pragma unroll
+            for (int s = 0; s < CH; ++s) {
+                if (t0 + s >= RPL) break;
+                Ring r;
+                ring_from_taps<T, LAZY>(tp[s], r, lane + (t0 + s) * GROUP < band.n);
+                make_poly<KIND>(r, rg[t0 + s]);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < CH; ++s) {
+                if (t0 + s >= RPL) break;
+                Ring r;
+                zero_ring(r);
+                make_poly<KIND>(r, rg[t0 + s]);
+            }
+        }
+    }
+}
+
+// Rings larger than the registers hold: position k is expanded into column k of
+// a region of rec_stride columns per coefficient, by lane k mod GROUP.
+template <typename T, int KIND, int GROUP, bool LAZY, int CHUNK = ring_chunk<T, GROUP>()>
+__device__ __forceinline__ void ring_to_region(const T* __restrict__ u, int H, int W, const RingBand& band, int lane,
+                                               const double* __restrict__ cpend, int nj, int pq,
+                                               double* __restrict__ rec, int rec_stride)
+{
+    constexpr int CH = CHUNK;
+    for (int k0 = lane; k0 < band.n; k0 += CH * GROUP) {
+        RingTaps<T, LAZY> tp[CH];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int k = k0 + s * GROUP;
+            int i, j;
+            band_at(band, k < band.n ? k : 0, i, j);
+            load_taps<T, LAZY>(u, H, W, i, j, band.r0, band.r1, band.c0, band.c1, tp[s], cpend, nj, pq);
+        }
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int k = k0 + s * GROUP;
+            if (k < band.n) {
+                Ring r;
+                PolyRing<KIND> pr;
+                ring_from_taps<T, LAZY>(tp[s], r);
+                make_poly<KIND>(r, pr);
+                store_poly<KIND>(rec, rec_stride, k, pr);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Block levels (b >= 2).  GROUP lanes per block; each lane keeps RPL ring
 // records in registers (RPL = 0: records are rebuilt from memory at every
@@ -658,7 +743,7 @@ struct CoarseArgs {
     int rec_stride;          // records per coefficient row of a region (8b)
 };
 
-template <typename T, int KIND, int GROUP, int RPL, bool LAZY, class GSum>
+template <typename T, int KIND, int GROUP, int RPL, bool LAZY, int CHUNK = ring_chunk<T, GROUP>(), class GSum>
 __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restrict__ f, int H, int W,
                                             int p, int q, int r0, int r1, int c0, int c1, int lane,
                                             double alpha, int M, int G, const GSum& gsum, const CoarseArgs& ca)
@@ -690,19 +775,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
     double cval;
     if (RPL > 0) {
         PolyRing<KIND> rg[RPL > 0 ? RPL : 1];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int k = lane + t * GROUP;
-            Ring r;
-            if (k < ncand) {
-                int i, j;
-                band_at(band, k, i, j);
-                make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, r, ca.cpend, ca.nj, pq);
-            } else {
-                zero_ring(r);
-            }
-            make_poly<KIND>(r, rg[t]);
-        }
+        ring_to_regs<T, KIND, GROUP, (RPL > 0 ? RPL : 1), LAZY, CHUNK>(u, H, W, band, lane, ca.cpend, ca.nj, pq, rg);
         const double fs = gsum(rsum) / s;
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
@@ -729,15 +802,7 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
         // rings larger than the registers hold: each lane expands its records once into the
         // block's region and reads them back (only its own) at every evaluation, in the same
         // order as the rebuilding loop below
-        for (int kk = lane; kk < ncand; kk += GROUP) {
-            int i, j;
-            Ring rr;
-            PolyRing<KIND> pr;
-            band_at(band, kk, i, j);
-            make_ring<T, LAZY>(u, H, W, i, j, r0, r1, c0, c1, rr, ca.cpend, ca.nj, pq);
-            make_poly<KIND>(rr, pr);
-            store_poly<KIND>(ca.rec, ca.rec_stride, kk, pr);
-        }
+        ring_to_region<T, KIND, GROUP, LAZY, CHUNK>(u, H, W, band, lane, ca.cpend, ca.nj, pq, ca.rec, ca.rec_stride);
         const double fs = gsum(rsum) / s;
         auto Kpart = [&](const auto& cs, auto& out) {
             constexpr int N = sizeof(out) / sizeof(double);
@@ -871,9 +936,10 @@ __device__ __forceinline__ void solve_b2_item(T* __restrict__ u, const T* __rest
     if (interior) {
         solve_block2_interior<T, KIND, QL>(u, f, H, W, r0, c0, lane, alpha, M, G);
     } else {
+        // one record at a time: the few border blocks must not raise the registers of the kernel
         const CoarseArgs ca{nullptr, 0, nullptr, 0, nullptr, 16};
-        solve_block<T, KIND, QL, 16 / QL, false>(u, f, H, W, p, q, r0, min(r0 + 2, H), c0, min(c0 + 2, W), lane,
-                                                 alpha, M, G, WaveSum<QL>(), ca);
+        solve_block<T, KIND, QL, 16 / QL, false, 1>(u, f, H, W, p, q, r0, min(r0 + 2, H), c0, min(c0 + 2, W), lane,
+                                                    alpha, M, G, WaveSum<QL>(), ca);
     }
 }
 
