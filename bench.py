@@ -106,7 +106,7 @@ def parse():
 
 
 # the sources the colour-sweep kernels are compiled from (their counters are void once these change)
-SWEEP_SOURCES = ("mgc_device.h", "mgc_internal.h", "mgc_sweep.h", "mgc_kernels.hip")
+SWEEP_SOURCES = ("mgc_device.h", "mgc_internal.h", "mgc_sweep.h", "mgc_kernels.hip", "mgc_split.hip")
 
 
 def kernel_sources_sha() -> str:
