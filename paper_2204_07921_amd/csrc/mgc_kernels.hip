@@ -118,23 +118,43 @@ __global__ __launch_bounds__(256) void block_sums_kernel(T* __restrict__ u, cons
     const int n = (rb > ra ? rb - ra : 0) * w;
     // element t = threadIdx.x + m blockDim.x of the chunk is pixel (ra + t / w, c0 + t % w);
     // its row and column advance by the step's quotient and remainder
-    const int si = (int)blockDim.x / w, sj = (int)blockDim.x - si * w;
+    // U elements per round have their loads in flight together (one at a time, each waited on
+    // its memory round trip); they are then applied and summed in the order of t.  Elements past
+    // the chunk's end take the first element's address and are skipped.
+    constexpr int U = 8;
+    const int B = (int)blockDim.x;
+    const int si = B / w, sj = B - si * w;
     int i = ra + (int)threadIdx.x / w, j = c0 + (int)threadIdx.x % w;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const size_t idx = (size_t)i * W + j;
-        double v = (double)u[idx];
-        if (cprev) {
-            const double c = cprev[(size_t)side_div(i, bp, lbp) * njp + side_div(j, bp, lbp)];
-            if (c != 0.0) {
-                const T r = (T)(v + c);
-                u[idx] = r;
+    for (int t0 = threadIdx.x; t0 < n; t0 += U * B) {
+        int pi[U], pj[U];
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            const bool ok = m == 0 || t0 + m * B < n;   // element 0 is in the chunk (t0 < n)
+            pi[m] = ok ? i : pi[0];
+            pj[m] = ok ? j : pj[0];
+            i += si;
+            j += sj;
+            if (j >= c1) { j -= w; ++i; }
+        }
+        double uv[U], fv[U], cv[U];
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            const size_t idx = (size_t)pi[m] * W + pj[m];
+            uv[m] = (double)u[idx];
+            fv[m] = (double)f[idx];
+            cv[m] = cprev ? cprev[(size_t)side_div(pi[m], bp, lbp) * njp + side_div(pj[m], bp, lbp)] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            if (t0 + m * B >= n) break;
+            double v = uv[m];
+            if (cv[m] != 0.0) {
+                const T r = (T)(v + cv[m]);
+                u[(size_t)pi[m] * W + pj[m]] = r;
                 v = (double)r;
             }
+            acc += fv[m] - v;
         }
-        acc += (double)f[idx] - v;
-        i += si;
-        j += sj;
-        if (j >= c1) { j -= w; ++i; }
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);

@@ -155,12 +155,10 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
                     for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(rg[t], cs[k]);
                 }
         } else {
-            for (int kk = lane; kk < ncand; kk += GROUP) {
-                PolyRing<KIND> pr;
-                load_poly<KIND>(rec, ca.rec_stride, kk, pr);
+            for_region_records<KIND, GROUP>(rec, ca.rec_stride, ncand, lane, [&](const PolyRing<KIND>& pr) {
 #pragma unroll
                 for (int k = 0; k < N; ++k) out[k] += abs_poly<KIND>(pr, cs[k]);
-            }
+            });
         }
     };
     auto Dpart = [&](double c) {
@@ -170,11 +168,8 @@ __global__ __launch_bounds__(GROUP) void sweep_split_kernel(T* __restrict__ u, c
             for (int t = 0; t < RPL; ++t)
                 if (lane + t * GROUP < ncand) acc += dabs_poly<KIND>(rg[t], c);
         } else {
-            for (int kk = lane; kk < ncand; kk += GROUP) {
-                PolyRing<KIND> pr;
-                load_poly<KIND>(rec, ca.rec_stride, kk, pr);
-                acc += dabs_poly<KIND>(pr, c);
-            }
+            for_region_records<KIND, GROUP>(rec, ca.rec_stride, ncand, lane,
+                                            [&](const PolyRing<KIND>& pr) { acc += dabs_poly<KIND>(pr, c); });
         }
         return acc;
     };

@@ -650,6 +650,25 @@ constexpr int ring_chunk()
     return (GROUP >= 1024 ? 2 : 4) / (sizeof(T) == 8 ? 2 : 1);
 }
 
+// Records read back from a region at every evaluation: f(record) for the lane's
+// positions k = lane, lane + GROUP, ... in that order, with the loads of two
+// records in flight at once (one at a time, each waited on its round trip).  The
+// split solve's streamed kernel uses it; the one-workgroup streamed kernel has no
+// registers to spare for the second record.
+template <int KIND, int GROUP, class F>
+__device__ __forceinline__ void for_region_records(const double* __restrict__ rec, int stride, int ncand, int lane,
+                                                   F&& f)
+{
+    for (int k0 = lane; k0 < ncand; k0 += 2 * GROUP) {
+        const int k1 = k0 + GROUP;
+        PolyRing<KIND> p0, p1;
+        load_poly<KIND>(rec, stride, k0, p0);
+        load_poly<KIND>(rec, stride, k1 < ncand ? k1 : k0, p1);
+        f(p0);
+        if (k1 < ncand) f(p1);
+    }
+}
+
 // Slot t of a lane's registers holds band position lane + t GROUP.  Each chunk
 // sits under a branch on its first position: a chunk wholly past the band's end
 // takes the zero records without loading, and the compiler cannot hoist a later
