@@ -194,10 +194,25 @@ __global__ __launch_bounds__(256) void batch_block_sums_kernel(const float* __re
         const int rb = min(min(ra + rows_per, (p + 1) * b), im.H);
         const int cnt = (rb > ra ? rb - ra : 0) * w;
         double acc = 0.0;
-        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-            const int i = ra + t / w, j = c0 + t % w;
-            const size_t idx = (size_t)im.off + (size_t)i * im.W + j;
-            acc += (double)f[idx] - (double)u[idx];
+        // U elements per round have their loads in flight together; they are summed in the
+        // order of t (elements past the chunk's end take element t0's address and are skipped)
+        constexpr int U = 8;
+        const int B = (int)blockDim.x;
+        for (int t0 = threadIdx.x; t0 < cnt; t0 += U * B) {
+            double fv[U], uv[U];
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                const int t = (m == 0 || t0 + m * B < cnt) ? t0 + m * B : t0;
+                const int i = ra + t / w, j = c0 + t % w;
+                const size_t idx = (size_t)im.off + (size_t)i * im.W + j;
+                fv[m] = (double)f[idx];
+                uv[m] = (double)u[idx];
+            }
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                if (t0 + m * B >= cnt) break;
+                acc += fv[m] - uv[m];
+            }
         }
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
@@ -227,10 +242,28 @@ __global__ __launch_bounds__(256) void batch_apply_kernel(float* __restrict__ u,
     const double* cp = cpend + pend_off[img];
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     if (t0 >= n) return;
+    // U pixels per round have their loads in flight together (past n: pixel t0's address, skipped)
+    constexpr int U = 4;
     PixelWalk pw(t0, stride, im.W);
-    for (size_t t = t0; t < n; t += stride, pw.next()) {
-        const double c = cp[(size_t)side_div(pw.i, b, lb) * nj + side_div(pw.j, b, lb)];
-        if (c != 0.0) u[im.off + t] = (float)((double)u[im.off + t] + c);
+    for (size_t t = t0; t < n; t += U * stride) {
+        size_t px[U];
+        double c[U];
+        float uv[U];
+        const int i0 = pw.i, j0 = pw.j;
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            const bool ok = m == 0 || t + m * stride < n;
+            const int i = ok ? pw.i : i0, j = ok ? pw.j : j0;
+            px[m] = im.off + (ok ? t + m * stride : t);
+            c[m] = cp[(size_t)side_div(i, b, lb) * nj + side_div(j, b, lb)];
+            uv[m] = u[px[m]];
+            pw.next();
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            if (t + m * stride >= n) break;
+            if (c[m] != 0.0) u[px[m]] = (float)((double)uv[m] + c[m]);
+        }
     }
 }
 

@@ -171,10 +171,28 @@ __global__ __launch_bounds__(256) void apply_level_kernel(T* __restrict__ u, int
     const size_t n = (size_t)H * W;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     if (t0 >= n) return;
+    // U pixels per round have their loads in flight together (past n: pixel t0's address, skipped)
+    constexpr int U = 4;
     PixelWalk pw(t0, stride, W);
-    for (size_t t = t0; t < n; t += stride, pw.next()) {
-        const double c = cpend[(size_t)side_div(pw.i, b, lb) * nj + side_div(pw.j, b, lb)];
-        if (c != 0.0) u[t] = (T)((double)u[t] + c);
+    for (size_t t = t0; t < n; t += U * stride) {
+        size_t px[U];
+        double c[U];
+        T uv[U];
+        const int i0 = pw.i, j0 = pw.j;
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            const bool ok = m == 0 || t + m * stride < n;
+            const int i = ok ? pw.i : i0, j = ok ? pw.j : j0;
+            px[m] = ok ? t + m * stride : t;
+            c[m] = cpend[(size_t)side_div(i, b, lb) * nj + side_div(j, b, lb)];
+            uv[m] = u[px[m]];
+            pw.next();
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            if (t + m * stride >= n) break;
+            if (c[m] != 0.0) u[px[m]] = (T)((double)uv[m] + c[m]);
+        }
     }
 }
 

@@ -762,6 +762,26 @@ struct CoarseArgs {
     int rec_stride;          // records per coefficient row of a region (8b)
 };
 
+// Fine block levels walk their block's pixels (sum of f - u, then the update) in
+// rounds of BLOCK_UNROLL elements per lane: block_walk gives the addresses of
+// elements k0, k0 + GROUP, ... of a round (elements past n take element k0's
+// address and are skipped by the caller) and advances the walk (i, j) by the
+// round.
+constexpr int BLOCK_UNROLL = 4;
+
+template <int GROUP>
+__device__ __forceinline__ void block_walk(int k0, int n, int& i, int& j, int si, int sj, int c1, int w, int W,
+                                           size_t (&idx)[BLOCK_UNROLL])
+{
+#pragma unroll
+    for (int m = 0; m < BLOCK_UNROLL; ++m) {
+        idx[m] = (m == 0 || k0 + m * GROUP < n) ? (size_t)i * W + j : idx[0];
+        i += si;
+        j += sj;
+        if (j >= c1) { j -= w; ++i; }
+    }
+}
+
 template <typename T, int KIND, int GROUP, int RPL, bool LAZY, int CHUNK = ring_chunk<T, GROUP>(), class GSum>
 __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restrict__ f, int H, int W,
                                             int p, int q, int r0, int r1, int c0, int c1, int lane,
@@ -773,15 +793,24 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
         const double* part = ca.partials + ((size_t)p * ca.nj + q) * ca.nchunk;
         for (int k = lane; k < ca.nchunk; k += GROUP) rsum += part[k];
     } else {
-        // element k = lane + m GROUP is pixel (r0 + k / w, c0 + k % w), advanced incrementally
+        // element k = lane + m GROUP is pixel (r0 + k / w, c0 + k % w), advanced incrementally;
+        // BLOCK_UNROLL elements have their loads in flight together and are summed in order
         const int si = GROUP / w, sj = GROUP - si * w;
         int i = r0 + lane / w, j = c0 + lane % w;
-        for (int k = lane; k < h * w; k += GROUP) {
-            const size_t idx = (size_t)i * W + j;
-            rsum += (double)f[idx] - (double)u[idx];
-            i += si;
-            j += sj;
-            if (j >= c1) { j -= w; ++i; }
+        for (int k0 = lane; k0 < h * w; k0 += BLOCK_UNROLL * GROUP) {
+            size_t idx[BLOCK_UNROLL];
+            block_walk<GROUP>(k0, h * w, i, j, si, sj, c1, w, W, idx);
+            double fv[BLOCK_UNROLL], uv[BLOCK_UNROLL];
+#pragma unroll
+            for (int m = 0; m < BLOCK_UNROLL; ++m) {
+                fv[m] = (double)f[idx[m]];
+                uv[m] = (double)u[idx[m]];
+            }
+#pragma unroll
+            for (int m = 0; m < BLOCK_UNROLL; ++m) {
+                if (k0 + m * GROUP >= h * w) break;
+                rsum += fv[m] - uv[m];
+            }
         }
     }
     // the group total of rsum (and with it f*) is taken after the ring records are built, so the
@@ -881,12 +910,17 @@ __device__ __forceinline__ void solve_block(T* __restrict__ u, const T* __restri
     } else if (cval != 0.0) {
         const int si = GROUP / w, sj = GROUP - si * w;
         int i = r0 + lane / w, j = c0 + lane % w;
-        for (int k = lane; k < h * w; k += GROUP) {
-            const size_t idx = (size_t)i * W + j;
-            u[idx] = (T)((double)u[idx] + cval);
-            i += si;
-            j += sj;
-            if (j >= c1) { j -= w; ++i; }
+        for (int k0 = lane; k0 < h * w; k0 += BLOCK_UNROLL * GROUP) {
+            size_t idx[BLOCK_UNROLL];
+            block_walk<GROUP>(k0, h * w, i, j, si, sj, c1, w, W, idx);
+            T uv[BLOCK_UNROLL];
+#pragma unroll
+            for (int m = 0; m < BLOCK_UNROLL; ++m) uv[m] = u[idx[m]];
+#pragma unroll
+            for (int m = 0; m < BLOCK_UNROLL; ++m) {
+                if (k0 + m * GROUP >= h * w) break;
+                u[idx[m]] = (T)((double)uv[m] + cval);
+            }
         }
     }
 }
