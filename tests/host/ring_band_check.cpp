@@ -4,7 +4,8 @@
 // pixel, i.e. every pixel whose nine clamped taps lie partly inside and partly outside the block
 // (brute force).  For every candidate's clamped taps, tap_block (the coarse levels' lookup of a
 // tap's pending correction) equals the block index by division.  The b = 2 split of a colour's
-// blocks into border and interior ones (split2) is checked against its definition.
+// blocks into border and interior ones (split2) is checked against its definition, and the
+// sign-bit side tests (side_of, inside_of) against comparisons.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -88,6 +89,19 @@ int main()
                         ++bad;
                     }
                 }
+    // the sign-bit side tests behind tap_block and the in-block tap mask, against comparisons
+    // (every v near and across the interval, intervals from width 1 up to wide image spans)
+    for (int lo = -3; lo <= 40; ++lo)
+        for (int hi : {lo + 1, lo + 2, lo + 3, lo + 7, lo + 64, lo + 1000, 1 << 30})
+            for (int v = -70; v <= 1100; ++v) {
+                const int side = v < lo ? -1 : (v >= hi ? 1 : 0);
+                const int in = (v >= lo && v < hi) ? 1 : 0;
+                ++cases;
+                if (mgc::side_of(v, lo, hi) != side || mgc::inside_of(v, lo, hi) != in) {
+                    if (bad < 5) std::printf("side_of/inside_of v %d lo %d hi %d\n", v, lo, hi);
+                    ++bad;
+                }
+            }
     std::printf("cases %ld bad %ld\n", cases, bad);
     return bad == 0 ? 0 : 1;
 }
