@@ -284,12 +284,29 @@ __global__ __launch_bounds__(256) void batch_energy_partial_kernel(const float* 
     double acc = 0.0;
     const size_t p0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     if (p0 < n) {
+        // U pixels per round have their loads in flight together and are summed in the order of
+        // p; a pixel past n repeats pixel p's window and adds 0.0 (every term is >= 0, so the sum
+        // is bitwise the one without it), which keeps the loads out of a branch
+        constexpr int U = 2;
         PixelWalk pw(p0, stride, im.W);
-        for (size_t p = p0; p < n; p += stride, pw.next()) {
-            const double d = (double)uu[p] - (double)ff[p];
-            const double k = im.kind == 0 ? abs_kappa_at<0>(uu, im.H, im.W, pw.i, pw.j)
-                                          : abs_kappa_at<1>(uu, im.H, im.W, pw.i, pw.j);
-            acc += k + 0.5 * im.alpha * d * d;
+        for (size_t p = p0; p < n; p += U * stride) {
+            float v[U][3][3], fv[U];
+            const int i0 = pw.i, j0 = pw.j;
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                const bool ok = m == 0 || p + m * stride < n;
+                const int i = ok ? pw.i : i0, j = ok ? pw.j : j0;
+                load_window(uu, im.H, im.W, i, j, v[m]);
+                fv[m] = ff[(size_t)i * im.W + j];
+                pw.next();
+            }
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                const double d = (double)v[m][1][1] - (double)fv[m];
+                const double k = im.kind == 0 ? abs_kappa_window<0>(v[m]) : abs_kappa_window<1>(v[m]);
+                const double e = k + 0.5 * im.alpha * d * d;
+                acc += (m == 0 || p + m * stride < n) ? e : 0.0;
+            }
         }
     }
 #pragma unroll

@@ -293,23 +293,42 @@ __device__ __forceinline__ double dabs_poly(const PolyRing<KIND>& p, double c)
     }
 }
 
-// |kappa| at pixel (i, j) of the unshifted image (energy kernel).
-template <int KIND, typename T>
-__device__ __forceinline__ double abs_kappa_at(const T* __restrict__ u, int H, int W, int i, int j)
+// The 3x3 clamped window of u around (i, j), loaded (kept apart from the
+// arithmetic so that a loop can have the loads of several windows in flight).
+template <typename T>
+__device__ __forceinline__ void load_window(const T* __restrict__ u, int H, int W, int i, int j, T (&v)[3][3])
 {
-    double t[3][3];
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
         const int ci = clampi(i + dy, 0, H - 1);
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx)
-            t[dy + 1][dx + 1] = (double)u[(size_t)ci * W + clampi(j + dx, 0, W - 1)];
+        for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = u[(size_t)ci * W + clampi(j + dx, 0, W - 1)];
     }
+}
+
+// |kappa| of the window's centre pixel.
+template <int KIND, typename T>
+__device__ __forceinline__ double abs_kappa_window(const T (&v)[3][3])
+{
+    double t[3][3];
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+        for (int x = 0; x < 3; ++x) t[y][x] = (double)v[y][x];
     Ring r;
     stencil5(t, r.a);
 #pragma unroll
     for (int k = 0; k < 5; ++k) r.b[k] = 0.0;
     return abs_kappa<KIND>(r, 0.0);
+}
+
+// |kappa| at pixel (i, j) of the unshifted image (energy kernel).
+template <int KIND, typename T>
+__device__ __forceinline__ double abs_kappa_at(const T* __restrict__ u, int H, int W, int i, int j)
+{
+    T v[3][3];
+    load_window(u, H, W, i, j, v);
+    return abs_kappa_window<KIND>(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -209,10 +209,28 @@ __global__ __launch_bounds__(256) void energy_partial_kernel(const T* __restrict
     double acc = 0.0;
     const size_t p0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     if (p0 < n) {
+        // U pixels per round have their loads in flight together and are summed in the order of
+        // p; a pixel past n repeats pixel p's window and adds 0.0 (every term is >= 0, so the sum
+        // is bitwise the one without it), which keeps the loads out of a branch
+        constexpr int U = 2;
         PixelWalk pw(p0, stride, W);
-        for (size_t p = p0; p < n; p += stride, pw.next()) {
-            const double d = (double)u[p] - (double)f[p];
-            acc += abs_kappa_at<KIND>(u, H, W, pw.i, pw.j) + 0.5 * alpha * d * d;
+        for (size_t p = p0; p < n; p += U * stride) {
+            T v[U][3][3], fv[U];
+            const int i0 = pw.i, j0 = pw.j;
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                const bool ok = m == 0 || p + m * stride < n;
+                const int i = ok ? pw.i : i0, j = ok ? pw.j : j0;
+                load_window(u, H, W, i, j, v[m]);
+                fv[m] = f[(size_t)i * W + j];
+                pw.next();
+            }
+#pragma unroll
+            for (int m = 0; m < U; ++m) {
+                const double d = (double)v[m][1][1] - (double)fv[m];
+                const double e = abs_kappa_window<KIND>(v[m]) + 0.5 * alpha * d * d;
+                acc += (m == 0 || p + m * stride < n) ? e : 0.0;
+            }
         }
     }
 #pragma unroll
@@ -229,10 +247,26 @@ __global__ __launch_bounds__(256) void diff_norms_kernel(const T* __restrict__ u
 {
     __shared__ double lds[8];
     double a = 0.0, b = 0.0;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
-        const double x = (double)u[p], d = x - (double)prev[p];
-        a += d * d;
-        b += x * x;
+    // U elements per round have their loads in flight together and are summed in the order of p;
+    // an element past n repeats element p and adds 0.0 (the terms are squares, so the sums are
+    // bitwise the ones without it), which keeps the loads out of a branch
+    constexpr int U = 4;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += U * stride) {
+        T uv[U], pv[U];
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            const size_t q = (m == 0 || p + m * stride < n) ? p + m * stride : p;
+            uv[m] = u[q];
+            pv[m] = prev[q];
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+            const bool ok = m == 0 || p + m * stride < n;
+            const double x = (double)uv[m], d = x - (double)pv[m];
+            a += ok ? d * d : 0.0;
+            b += ok ? x * x : 0.0;
+        }
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
